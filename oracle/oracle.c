@@ -1,0 +1,513 @@
+/*
+ * oracle.c -- plain, slow FP64 CPU reference solver ("the oracle") for the 3D
+ * Newtonian adiabatic finite-volume hydro update of AthenaK (Stone et al.
+ * 2024, arXiv:2409.16053).
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may link, load or
+ * call this file. Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg use it. It shares no source with the GPU path.
+ *
+ * What it computes, in the paper's order (Sec. 3, "reconstruct, solve, and
+ * advance"):
+ *   ghost-zone fill (Sec. 2, boundary conditions)
+ *   -> conserved to primitive, W = [rho, v, u_g], p = (gamma-1) u_g (Sec. 3.1, Eq. 4)
+ *   -> reconstruction on primitives, PLM or PPM4 (Sec. 3)
+ *   -> HLLC Riemann fluxes in x, y and z (Sec. 3; Toro's textbook, Ch. 10)
+ *   -> flux divergence and a low-storage SSP-RK2 stage (Sec. 3, method of lines)
+ *   -> CFL time step, Eq. 3: CFL times the minimum over all cells and all
+ *      dimensions of dx_d / lambda_max,d.
+ * It works on the whole mesh with no MeshBlock decomposition: splitting the
+ * mesh into blocks changes no per-cell arithmetic.
+ *
+ * Readings where the paper is silent (each is listed with its reason in the
+ * design notes): PLM uses the van Leer harmonic-mean limiter; PPM4 is
+ * Colella & Woodward (1984) Eqs. 1.6-1.10 without steepening or flattening;
+ * the reconstructed energy variable is u_g; HLLC is Toro-Spruce-Speares with
+ * PVRS pressure-based wave speeds; RK2 is SSPRK(2,2) in low-storage form;
+ * lambda_d = |v_d| + c_s; floors act on W only and never change U; outflow is
+ * a zero-gradient copy of U.
+ *
+ * Plain loops, FP64, compiled with -ffp-contract=off. Optional OpenMP over
+ * k-planes: every cell's arithmetic is independent of the thread count and
+ * the time-step minimum is exact, so results do not depend on it.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { OR_PERIODIC = 0, OR_OUTFLOW = 1 };
+enum { OR_PLM = 0, OR_PPM4 = 1 };
+enum { OR_OK = 0, OR_ERR_ARG = 1, OR_ERR_NOMEM = 2, OR_ERR_STATE = 4 };
+
+/* Problem description passed from Python (ctypes mirror in oracle/__init__.py). */
+typedef struct {
+  int32_t n[3];      /* interior cells nx, ny, nz                      */
+  int32_t bc[3][2];  /* per axis (lower, upper): OR_PERIODIC/OR_OUTFLOW */
+  int32_t recon;     /* OR_PLM (2 ghosts) or OR_PPM4 (3 ghosts)        */
+  int32_t pad_;
+  double dx[3];      /* cell widths                                    */
+  double gamma;      /* ratio of specific heats, > 1                   */
+  double cfl;        /* Courant number                                 */
+  double rho_floor;  /* density floor applied to W                     */
+  double p_floor;    /* pressure floor applied to W                    */
+} or_params;
+
+/* A stored array with ghosts: [5][nz+2g][ny+2g][nx+2g]. */
+typedef struct {
+  int n[3];
+  int g;
+  int s[3];      /* stored extent per axis */
+  size_t sv;     /* stride of one variable */
+} grid;
+
+static void grid_init(grid* G, const or_params* p, int g) {
+  for (int d = 0; d < 3; ++d) { G->n[d] = p->n[d]; G->s[d] = p->n[d] + 2 * g; }
+  G->g = g;
+  G->sv = (size_t)G->s[0] * G->s[1] * G->s[2];
+}
+
+/* index of variable v at cell (i,j,k); i,j,k in [-g, n+g) */
+static size_t at(const grid* G, int v, int i, int j, int k) {
+  return (size_t)v * G->sv +
+         ((size_t)(k + G->g) * G->s[1] + (size_t)(j + G->g)) * G->s[0] + (size_t)(i + G->g);
+}
+
+int or_nghost(int recon) { return recon == OR_PPM4 ? 3 : 2; }
+
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int or_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------
+ * Ghost zones (Sec. 2, boundary conditions are applied through ghost cells).
+ * Periodic: the cell one period away. Outflow: the nearest interior cell
+ * (zero gradient). The x faces are filled first over the interior (j,k),
+ * then y over all i, then z over all (i,j), so edge and corner ghosts end up
+ * filled too, although the dimension-by-dimension stencil never reads them.
+ * ---------------------------------------------------------------------- */
+static int src_index(int c, int n, int bclo, int bchi) {
+  if (c < 0) return bclo == OR_PERIODIC ? ((c % n) + n) % n : 0;
+  if (c >= n) return bchi == OR_PERIODIC ? c % n : n - 1;
+  return c;
+}
+
+static void fill_ghosts(const or_params* p, const grid* G, double* U) {
+  const int g = G->g, nx = G->n[0], ny = G->n[1], nz = G->n[2];
+  for (int v = 0; v < 5; ++v) {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = -g; i < nx + g; ++i) {
+          if (i >= 0 && i < nx) continue;
+          int si = src_index(i, nx, p->bc[0][0], p->bc[0][1]);
+          U[at(G, v, i, j, k)] = U[at(G, v, si, j, k)];
+        }
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+      for (int j = -g; j < ny + g; ++j) {
+        if (j >= 0 && j < ny) continue;
+        int sj = src_index(j, ny, p->bc[1][0], p->bc[1][1]);
+        for (int i = -g; i < nx + g; ++i) U[at(G, v, i, j, k)] = U[at(G, v, i, sj, k)];
+      }
+#pragma omp parallel for schedule(static)
+    for (int k = -g; k < nz + g; ++k) {
+      if (k >= 0 && k < nz) continue;
+      int sk = src_index(k, nz, p->bc[2][0], p->bc[2][1]);
+      for (int j = -g; j < ny + g; ++j)
+        for (int i = -g; i < nx + g; ++i) U[at(G, v, i, j, k)] = U[at(G, v, i, j, sk)];
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * Conserved -> primitive (Sec. 3.1, Eq. 4): rho; v = M / rho;
+ * u_g = E - |M|^2 / (2 rho). Floors act on W only: rho below rho_floor is
+ * raised to it (and used for v and u_g), u_g below p_floor/(gamma-1) is raised
+ * to it. Returns 1 if a floor fired. *bad is set when U is non-finite or
+ * rho <= 0 (an unrecoverable state).
+ * ---------------------------------------------------------------------- */
+int or_c2p(const or_params* p, const double u[5], double w[5], int* bad) {
+  int hit = 0;
+  double rho = u[0];
+  if (bad) {
+    int b = 0;
+    for (int q = 0; q < 5; ++q) b |= !isfinite(u[q]);
+    b |= !(rho > 0.0);
+    *bad = b;
+  }
+  if (rho < p->rho_floor) { rho = p->rho_floor; hit = 1; }
+  double ke2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+  double ug = u[4] - 0.5 * ke2 / rho;
+  double ufloor = p->p_floor / (p->gamma - 1.0);
+  if (ug < ufloor) { ug = ufloor; hit = 1; }
+  w[0] = rho;
+  w[1] = u[1] / rho;
+  w[2] = u[2] / rho;
+  w[3] = u[3] / rho;
+  w[4] = ug;
+  return hit;
+}
+
+/* ------------------------------------------------------------------------
+ * Reconstruction (Sec. 3: always on primitive variables).
+ * ---------------------------------------------------------------------- */
+
+/* PLM: van Leer harmonic-mean limited slope of a cell from its neighbours;
+ * the cell's left and right face values are w0 -/+ slope/2. */
+void or_plm_cell(double wm, double w0, double wp, double* left, double* right) {
+  double dl = w0 - wm, dr = wp - w0;
+  double prod = dl * dr;
+  double slope = prod > 0.0 ? 2.0 * prod / (dl + dr) : 0.0;
+  *left = w0 - 0.5 * slope;
+  *right = w0 + 0.5 * slope;
+}
+
+/* PPM4 monotonised central slope (Colella & Woodward 1984, Eq. 1.8). */
+static double cw_slope(double wm, double w0, double wp) {
+  double dl = w0 - wm, dr = wp - w0;
+  if (!(dl * dr > 0.0)) return 0.0;
+  double da = 0.5 * (wp - wm);
+  double m = fabs(da);
+  if (2.0 * fabs(dl) < m) m = 2.0 * fabs(dl);
+  if (2.0 * fabs(dr) < m) m = 2.0 * fabs(dr);
+  return copysign(m, da);
+}
+
+/* PPM4 interface value between cells c and c+1 (CW84 Eq. 1.6, uniform mesh). */
+static double cw_interface(double wc, double wc1, double sc, double sc1) {
+  return wc + 0.5 * (wc1 - wc) - (sc1 - sc) / 6.0;
+}
+
+/* PPM4 face values of cell c from w[0..4] = cells c-2..c+2: interface values
+ * on both sides, then the monotonicity constraints of CW84 Eq. 1.10. */
+void or_ppm4_cell(const double w[5], double* left, double* right) {
+  double s_m = cw_slope(w[0], w[1], w[2]);
+  double s_0 = cw_slope(w[1], w[2], w[3]);
+  double s_p = cw_slope(w[2], w[3], w[4]);
+  double aL = cw_interface(w[1], w[2], s_m, s_0);
+  double aR = cw_interface(w[2], w[3], s_0, s_p);
+  double a = w[2];
+  if ((aR - a) * (a - aL) <= 0.0) {
+    aL = a;
+    aR = a;
+  } else {
+    double d = aR - aL;
+    double m6 = d * (a - 0.5 * (aL + aR));
+    double d26 = d * d / 6.0;
+    if (m6 > d26) aL = 3.0 * a - 2.0 * aR;
+    else if (-d26 > m6) aR = 3.0 * a - 2.0 * aL;
+  }
+  *left = aL;
+  *right = aR;
+}
+
+/* ------------------------------------------------------------------------
+ * HLLC Riemann solver (Sec. 3 names HLLC; the Toro-Spruce-Speares solver of
+ * Toro's textbook Ch. 10 with PVRS pressure-based wave-speed estimates).
+ * States are primitive [rho, u_n, u_t1, u_t2, p]; the flux is
+ * [mass, normal momentum, t1 momentum, t2 momentum, energy].
+ * ---------------------------------------------------------------------- */
+void or_hllc(double gamma, const double wl[5], const double wr[5], double f[5]) {
+  const double rl = wl[0], ul = wl[1], vl = wl[2], zl = wl[3], pl = wl[4];
+  const double rr = wr[0], ur = wr[1], vr = wr[2], zr = wr[3], pr = wr[4];
+  const double gm1 = gamma - 1.0;
+  const double el = pl / gm1 + 0.5 * rl * (ul * ul + vl * vl + zl * zl);
+  const double er = pr / gm1 + 0.5 * rr * (ur * ur + vr * vr + zr * zr);
+  const double al = sqrt(gamma * pl / rl), ar = sqrt(gamma * pr / rr);
+
+  /* PVRS estimate of the star pressure, clipped at zero */
+  double ppv = 0.5 * (pl + pr) - 0.5 * (ur - ul) * (0.5 * (rl + rr)) * (0.5 * (al + ar));
+  double ps = ppv > 0.0 ? ppv : 0.0;
+  double ql = ps <= pl ? 1.0 : sqrt(1.0 + (gamma + 1.0) / (2.0 * gamma) * (ps / pl - 1.0));
+  double qr = ps <= pr ? 1.0 : sqrt(1.0 + (gamma + 1.0) / (2.0 * gamma) * (ps / pr - 1.0));
+  double sl = ul - al * ql, sr = ur + ar * qr;
+  double sstar = (pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur)) /
+                 (rl * (sl - ul) - rr * (sr - ur));
+
+  double fl[5] = {rl * ul, rl * ul * ul + pl, rl * ul * vl, rl * ul * zl, ul * (el + pl)};
+  double fr[5] = {rr * ur, rr * ur * ur + pr, rr * ur * vr, rr * ur * zr, ur * (er + pr)};
+
+  /* selection and tie-breaks: S_L >= 0 -> F_L; S* >= 0 -> F*_L;
+   * S_R > 0 -> F*_R; otherwise F_R */
+  if (sl >= 0.0) {
+    memcpy(f, fl, sizeof fl);
+    return;
+  }
+  if (!(sstar >= 0.0) && !(sr > 0.0)) {
+    memcpy(f, fr, sizeof fr);
+    return;
+  }
+  /* star state on the side of the contact that holds the face */
+  const int left = sstar >= 0.0;
+  const double rk = left ? rl : rr, uk = left ? ul : ur, vk = left ? vl : vr;
+  const double zk = left ? zl : zr, pk = left ? pl : pr, ek = left ? el : er;
+  const double sk = left ? sl : sr;
+  const double* fk = left ? fl : fr;
+  double fac = rk * (sk - uk) / (sk - sstar);
+  double us[5];
+  us[0] = fac;
+  us[1] = fac * sstar;
+  us[2] = fac * vk;
+  us[3] = fac * zk;
+  us[4] = fac * (ek / rk + (sstar - uk) * (sstar + pk / (rk * (sk - uk))));
+  double uk5[5] = {rk, rk * uk, rk * vk, rk * zk, ek};
+  for (int q = 0; q < 5; ++q) f[q] = fk[q] + sk * (us[q] - uk5[q]);
+}
+
+/* ------------------------------------------------------------------------
+ * One stage's flux divergence L(U) on interior cells (method of lines).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  grid G;          /* ghosted state / primitive arrays */
+  double* U;       /* ghosted conserved state          */
+  double* W;       /* ghosted primitives (rho, v, u_g) */
+  double* F[3];    /* face fluxes per direction        */
+  double* L;       /* divergence, interior [5][nz][ny][nx] */
+  size_t fsv[3];   /* flux variable strides            */
+} work;
+
+static size_t ncell(const or_params* p) { return (size_t)p->n[0] * p->n[1] * p->n[2]; }
+
+static size_t lin(const or_params* p, int i, int j, int k) {
+  return ((size_t)k * p->n[1] + j) * p->n[0] + i;
+}
+
+static int work_alloc(work* w, const or_params* p) {
+  memset(w, 0, sizeof *w);
+  grid_init(&w->G, p, or_nghost(p->recon));
+  size_t st = 5 * w->G.sv;
+  w->U = malloc(st * sizeof(double));
+  w->W = malloc(st * sizeof(double));
+  w->L = malloc(5 * ncell(p) * sizeof(double));
+  for (int d = 0; d < 3; ++d) {
+    size_t nf = (size_t)(p->n[0] + (d == 0)) * (p->n[1] + (d == 1)) * (p->n[2] + (d == 2));
+    w->fsv[d] = nf;
+    w->F[d] = malloc(5 * nf * sizeof(double));
+  }
+  if (!w->U || !w->W || !w->L || !w->F[0] || !w->F[1] || !w->F[2]) return OR_ERR_NOMEM;
+  return OR_OK;
+}
+
+static void work_free(work* w) {
+  free(w->U); free(w->W); free(w->L);
+  for (int d = 0; d < 3; ++d) free(w->F[d]);
+}
+
+/* Face states along direction d for the face between cells c-1 and c at
+ * transverse position (i,j,k) with the normal index replaced by c. */
+static void face_states(const or_params* p, const work* w, int d, int i, int j, int k,
+                        double wl[5], double wr[5]) {
+  const grid* G = &w->G;
+  const int di = d == 0, dj = d == 1, dk = d == 2;
+  for (int v = 0; v < 5; ++v) {
+    double s[6];
+    if (p->recon == OR_PLM) {
+      for (int o = -2; o <= 1; ++o) s[o + 2] = w->W[at(G, v, i + o * di, j + o * dj, k + o * dk)];
+      double l0, r0, l1, r1;
+      or_plm_cell(s[0], s[1], s[2], &l0, &r0); /* cell c-1 */
+      or_plm_cell(s[1], s[2], s[3], &l1, &r1); /* cell c   */
+      wl[v] = r0;
+      wr[v] = l1;
+    } else {
+      for (int o = -3; o <= 2; ++o) s[o + 3] = w->W[at(G, v, i + o * di, j + o * dj, k + o * dk)];
+      double l0, r0, l1, r1;
+      or_ppm4_cell(&s[0], &l0, &r0); /* cell c-1: cells c-3..c+1 */
+      or_ppm4_cell(&s[1], &l1, &r1); /* cell c:   cells c-2..c+2 */
+      wl[v] = r0;
+      wr[v] = l1;
+    }
+  }
+}
+
+/* Riemann flux at one face along d: rotate so the normal velocity comes
+ * first, form p = (gamma-1) u_g, solve, rotate back into (Mx, My, Mz). */
+static void face_flux(const or_params* p, int d, const double wl[5], const double wr[5],
+                      double out[5]) {
+  const int n = 1 + d, t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
+  double ql[5] = {wl[0], wl[n], wl[t1], wl[t2], (p->gamma - 1.0) * wl[4]};
+  double qr[5] = {wr[0], wr[n], wr[t1], wr[t2], (p->gamma - 1.0) * wr[4]};
+  double f[5];
+  or_hllc(p->gamma, ql, qr, f);
+  out[0] = f[0];
+  out[n] = f[1];
+  out[t1] = f[2];
+  out[t2] = f[3];
+  out[4] = f[4];
+}
+
+/* L(U) for the interior state Uin[5][nz][ny][nx]. Returns floor hits on
+ * interior cells; sets *bad if any interior cell is unrecoverable. */
+static long long divergence(const or_params* p, work* w, const double* Uin, int* bad) {
+  const grid* G = &w->G;
+  const int nx = p->n[0], ny = p->n[1], nz = p->n[2], g = G->g;
+  const size_t nc = ncell(p);
+  long long hits = 0;
+  int anybad = 0;
+
+  /* copy the interior into the ghosted array, then fill the ghosts */
+  for (int v = 0; v < 5; ++v) {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) w->U[at(G, v, i, j, k)] = Uin[v * nc + lin(p, i, j, k)];
+  }
+  fill_ghosts(p, G, w->U);
+
+  /* primitives on every stored cell */
+#pragma omp parallel for schedule(static) reduction(+ : hits) reduction(| : anybad)
+  for (int k = -g; k < nz + g; ++k)
+    for (int j = -g; j < ny + g; ++j)
+      for (int i = -g; i < nx + g; ++i) {
+        double u[5], q[5];
+        int b = 0;
+        for (int v = 0; v < 5; ++v) u[v] = w->U[at(G, v, i, j, k)];
+        int h = or_c2p(p, u, q, &b);
+        for (int v = 0; v < 5; ++v) w->W[at(G, v, i, j, k)] = q[v];
+        int interior = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+        if (interior) {
+          hits += h;
+          anybad |= b;
+        }
+      }
+
+  /* fluxes in x, y, z */
+  for (int d = 0; d < 3; ++d) {
+    const int fx = nx + (d == 0), fy = ny + (d == 1), fz = nz + (d == 2);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < fz; ++k)
+      for (int j = 0; j < fy; ++j)
+        for (int i = 0; i < fx; ++i) {
+          double wl[5], wr[5], f[5];
+          face_states(p, w, d, i, j, k, wl, wr);
+          face_flux(p, d, wl, wr, f);
+          for (int v = 0; v < 5; ++v) w->F[d][(size_t)v * w->fsv[d] + ((size_t)k * fy + j) * fx + i] = f[v];
+        }
+  }
+
+  /* L = -(Fx+ - Fx-)/dx - (Fy+ - Fy-)/dy - (Fz+ - Fz-)/dz, summed x, y, z */
+  for (int v = 0; v < 5; ++v) {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          const double* Fx = w->F[0] + (size_t)v * w->fsv[0];
+          const double* Fy = w->F[1] + (size_t)v * w->fsv[1];
+          const double* Fz = w->F[2] + (size_t)v * w->fsv[2];
+          size_t xm = ((size_t)k * ny + j) * (nx + 1) + i;
+          size_t ym = ((size_t)k * (ny + 1) + j) * nx + i;
+          size_t zm = ((size_t)k * ny + j) * nx + i;
+          double l = -(Fx[xm + 1] - Fx[xm]) / p->dx[0];
+          l -= (Fy[ym + nx] - Fy[ym]) / p->dx[1];
+          l -= (Fz[zm + (size_t)nx * ny] - Fz[zm]) / p->dx[2];
+          w->L[v * nc + lin(p, i, j, k)] = l;
+        }
+  }
+  if (bad) *bad = anybad;
+  return hits;
+}
+
+/* ------------------------------------------------------------------------
+ * CFL time step (Sec. 3, Eq. 3): CFL * min over interior cells and
+ * dimensions of dx_d / (|v_d| + c_s), c_s = sqrt(gamma p / rho).
+ * ---------------------------------------------------------------------- */
+double or_new_dt(const or_params* p, const double* U) {
+  const size_t nc = ncell(p);
+  double m = INFINITY;
+#pragma omp parallel for schedule(static) reduction(min : m)
+  for (size_t c = 0; c < nc; ++c) {
+    double u[5], q[5];
+    for (int v = 0; v < 5; ++v) u[v] = U[v * nc + c];
+    or_c2p(p, u, q, NULL);
+    double pr = (p->gamma - 1.0) * q[4];
+    double cs = sqrt(p->gamma * pr / q[0]);
+    for (int d = 0; d < 3; ++d) {
+      double r = p->dx[d] / (fabs(q[1 + d]) + cs);
+      if (r < m) m = r;
+    }
+  }
+  return p->cfl * m;
+}
+
+/* ------------------------------------------------------------------------
+ * Advance U[5][nz][ny][nx] by nsteps SSP-RK2 steps (Sec. 3, method of lines,
+ * low-storage SSP-RK of Ketcheson 2010, two stages):
+ *   U1      = Un + dt L(Un)
+ *   U(n+1)  = Un/2 + U1/2 + dt L(U1)/2
+ * then dt for the next step from U(n+1). *dt carries the step size in and the
+ * next one out; *t and *floor_hits accumulate. Returns OR_ERR_STATE when an
+ * interior cell held a non-finite value or rho <= 0 (the step still runs).
+ * ---------------------------------------------------------------------- */
+int or_advance(const or_params* p, double* U, int nsteps, double* t, double* dt,
+               long long* floor_hits) {
+  if (!p || !U || !t || !dt || nsteps < 0) return OR_ERR_ARG;
+  for (int d = 0; d < 3; ++d) {
+    if (p->n[d] < 1) return OR_ERR_ARG;
+    if ((p->bc[d][0] == OR_PERIODIC) != (p->bc[d][1] == OR_PERIODIC)) return OR_ERR_ARG;
+  }
+  work w;
+  if (work_alloc(&w, p) != OR_OK) { work_free(&w); return OR_ERR_NOMEM; }
+  const size_t nt = 5 * ncell(p);
+  double* U1 = malloc(nt * sizeof(double));
+  if (!U1) { work_free(&w); return OR_ERR_NOMEM; }
+  int status = OR_OK;
+  long long hits = 0;
+  for (int s = 0; s < nsteps; ++s) {
+    const double h = *dt;
+    int bad = 0;
+    hits += divergence(p, &w, U, &bad);
+    if (bad) status = OR_ERR_STATE;
+#pragma omp parallel for schedule(static)
+    for (size_t c = 0; c < nt; ++c) U1[c] = U[c] + h * w.L[c];
+    hits += divergence(p, &w, U1, &bad);
+    if (bad) status = OR_ERR_STATE;
+#pragma omp parallel for schedule(static)
+    for (size_t c = 0; c < nt; ++c) U[c] = 0.5 * U[c] + 0.5 * U1[c] + 0.5 * h * w.L[c];
+    *t += h;
+    *dt = or_new_dt(p, U);
+  }
+  if (floor_hits) *floor_hits += hits;
+  free(U1);
+  work_free(&w);
+  return status;
+}
+
+/* L(U) alone, for tests: Uin interior [5][nz][ny][nx] -> L same layout. */
+int or_divergence(const or_params* p, const double* Uin, double* Lout, long long* floor_hits) {
+  work w;
+  if (work_alloc(&w, p) != OR_OK) { work_free(&w); return OR_ERR_NOMEM; }
+  int bad = 0;
+  long long h = divergence(p, &w, Uin, &bad);
+  memcpy(Lout, w.L, 5 * ncell(p) * sizeof(double));
+  if (floor_hits) *floor_hits = h;
+  work_free(&w);
+  return bad ? OR_ERR_STATE : OR_OK;
+}
+
+/* Ghost fill alone, for tests: Uin interior -> Uout ghosted [5][nz+2g][ny+2g][nx+2g]. */
+int or_fill_ghosts(const or_params* p, const double* Uin, double* Uout) {
+  grid G;
+  grid_init(&G, p, or_nghost(p->recon));
+  const size_t nc = ncell(p);
+  for (int v = 0; v < 5; ++v)
+    for (int k = 0; k < p->n[2]; ++k)
+      for (int j = 0; j < p->n[1]; ++j)
+        for (int i = 0; i < p->n[0]; ++i) Uout[at(&G, v, i, j, k)] = Uin[v * nc + lin(p, i, j, k)];
+  fill_ghosts(p, &G, Uout);
+  return OR_OK;
+}

@@ -1,0 +1,102 @@
+"""The reference solver's pins catch plausible mistakes.
+
+Each case plants one mistake (a dropped term, a wrong sign, index or operand)
+in a copy of ``oracle/oracle.c``, builds it on the CPU and runs a fast subset
+of the pins against it: at least one pin must fail. The planted copies live in
+a temporary directory and are never used for anything else.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import test_oracle_physics as phys
+import test_oracle_units as units
+from paper_2409_16053_amd import problems as P
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+# (name, original text, planted text)
+MUTANTS = [
+    ("hllc_energy_star_sign", "(sstar - uk) * (sstar + pk", "(sstar + uk) * (sstar + pk"),
+    ("hllc_right_speed_sign", "sr = ur + ar * qr", "sr = ur - ar * qr"),
+    ("hllc_sstar_dropped_term", "pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur)",
+     "pr - pl + rl * ul * (sl - ul)"),
+    ("hllc_pvrs_sign", "0.5 * (pl + pr) - 0.5 * (ur - ul)", "0.5 * (pl + pr) + 0.5 * (ur - ul)"),
+    ("plm_half_slope", "*right = w0 + 0.5 * slope;", "*right = w0 + slope;"),
+    ("plm_limiter_factor", "2.0 * prod / (dl + dr)", "prod / (dl + dr)"),
+    ("ppm4_interface_sixth", "(sc1 - sc) / 6.0", "(sc1 - sc) / 3.0"),
+    ("ppm4_monotone_swap", "aL = 3.0 * a - 2.0 * aR", "aL = 3.0 * a - 2.0 * aL"),
+    ("c2p_kinetic_half", "u[4] - 0.5 * ke2 / rho", "u[4] - ke2 / rho"),
+    ("c2p_wrong_velocity", "w[2] = u[2] / rho;", "w[2] = u[3] / rho;"),
+    ("divergence_wrong_width", "l -= (Fy[ym + nx] - Fy[ym]) / p->dx[1];",
+     "l -= (Fy[ym + nx] - Fy[ym]) / p->dx[0];"),
+    ("divergence_sign", "l -= (Fz[zm + (size_t)nx * ny] - Fz[zm]) / p->dx[2];",
+     "l += (Fz[zm + (size_t)nx * ny] - Fz[zm]) / p->dx[2];"),
+    ("rk2_stage2_weight", "0.5 * U[c] + 0.5 * U1[c] + 0.5 * h * w.L[c]",
+     "0.5 * U[c] + 0.5 * U1[c] + h * w.L[c]"),
+    ("ghost_periodic_offset", "return bchi == OR_PERIODIC ? c % n : n - 1;",
+     "return bchi == OR_PERIODIC ? (c + 1) % n : n - 1;"),
+    ("ghost_outflow_index", "return bclo == OR_PERIODIC ? ((c % n) + n) % n : 0;",
+     "return bclo == OR_PERIODIC ? ((c % n) + n) % n : 1;"),
+    ("unrotate_transposed", "  out[t1] = f[2];\n  out[t2] = f[3];", "  out[t1] = f[3];\n  out[t2] = f[2];"),
+    ("dt_signed_velocity", "p->dx[d] / (fabs(q[1 + d]) + cs)", "p->dx[d] / (q[1 + d] + cs)"),
+    ("dt_sound_speed_gamma", "sqrt(p->gamma * pr / q[0])", "sqrt(pr / q[0])"),
+    ("face_state_shift", "s[o + 2] = w->W[at(G, v, i + o * di", "s[o + 2] = w->W[at(G, v, i + (o + 1) * di"),
+]
+
+
+def _build(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    lib = tmp_path / f"lib{name}.so"
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-std=c11", "-shared",
+                           "-fPIC", str(path), "-o", str(lib), "-lm"])
+    return oracle.Oracle.from_path(str(lib))
+
+
+def _fast_pins(O):
+    """A quick subset of the pins, each given the planted build."""
+    yield lambda: units.test_plm_harmonic_mean_worked_example(O)
+    yield lambda: units.test_ppm4_cubic_interfaces_exact(O)
+    yield lambda: units.test_ppm4_overshoot_worked_example(O)
+    yield lambda: units.test_hllc_consistency(O, 5.0 / 3.0)
+    yield lambda: units.test_hllc_contact_resolution(O, 5.0 / 3.0)
+    yield lambda: units.test_hllc_mirror_symmetry(O, 5.0 / 3.0)
+    yield lambda: units.test_hllc_weak_jumps_match_godunov_to_second_order(O, 1.4)
+    yield lambda: units.test_c2p_roundtrip(O)
+    yield lambda: units.test_new_dt_closed_form(O)
+    for bcs in (((0, 0), (0, 0), (0, 0)), ((1, 1), (1, 1), (1, 1))):
+        yield lambda bcs=bcs: units.test_ghost_fill_matches_numpy_pad(O, P.PLM, bcs)
+    yield lambda: phys.test_uniform_state_preserved_bitwise(O, P.PLM, P.PERIODIC)
+    yield lambda: phys.test_periodic_conservation(O, P.PLM, "kh")
+    yield lambda: phys.test_sound_wave_second_order_1d_plm(O, 0)
+    yield lambda: phys.test_sod_converges_to_exact(O, 1.4, P.PLM)
+    yield lambda: phys.test_sod_axis_symmetry_bitwise(O, P.PLM)
+    yield lambda: phys.test_colliding_streams_two_shocks(O, P.PLM)
+    yield lambda: phys.test_shear_wave_advection(O, 0)
+
+
+def test_unplanted_build_passes_fast_pins(tmp_path):
+    O = _build(tmp_path, "clean", "int or_nghost", "int or_nghost")
+    for pin in _fast_pins(O):
+        pin()
+
+
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(tmp_path, name, old, new):
+    O = _build(tmp_path, name, old, new)
+    caught = []
+    for n, pin in enumerate(_fast_pins(O)):
+        try:
+            with np.errstate(all="ignore"):
+                pin()
+        except (AssertionError, FloatingPointError, ValueError, ZeroDivisionError) as e:
+            caught.append((n, type(e).__name__))
+            break
+    assert caught, f"no pin caught the planted mistake {name}"
