@@ -1,0 +1,169 @@
+/*
+ * hy.h -- C ABI of the MI355X (gfx950) 3D Newtonian adiabatic hydro update.
+ *
+ * The library advances the Euler equations dU/dt + div F(W) = 0 with
+ * U = [rho, rho v, E], F = [rho v, rho v v + p, (E + p) v], E = u_g + rho v^2/2,
+ * W = [rho, v, u_g] and the gamma-law EOS p = (gamma - 1) u_g (Stone et al.
+ * 2024, arXiv:2409.16053: Sec. 3, Eq. 1; Sec. 3.1, Eq. 4). The mesh is a
+ * uniform Cartesian grid (Sec. 2, "Cartesian coordinates only") cut into
+ * equal MeshBlocks that are processed together as one MeshBlockPack
+ * (Sec. 2, "MeshBlockPacks"; "Data locality"). Each step runs the paper's
+ * reconstruct-solve-advance sequence (Sec. 3): ghost zones (Sec. 2,
+ * "Boundary conditions"), cons-to-prim, PLM or PPM4 reconstruction on
+ * primitives, HLLC fluxes in x, y and z, flux divergence and a two-stage
+ * low-storage SSP Runge-Kutta update (method of lines), then the CFL time step
+ * of Sec. 3, Eq. 3 taken as a minimum over all cells and dimensions.
+ *
+ * Conventions for every call:
+ *  - Status codes are returned; nothing throws or aborts across the ABI.
+ *    Argument errors are reported at once. Errors raised on the device
+ *    (non-finite state, rho <= 0) are reported by the next hy_query or
+ *    hy_get_state. hy_last_error() gives a message for the last failure on
+ *    the calling thread.
+ *  - Streams are hipStream_t passed as void*; NULL means the default stream.
+ *    Calls marked "async" only enqueue work on that stream.
+ *  - The library allocates no device memory: every problem lives in a
+ *    caller-owned device workspace of hy_workspace_bytes() bytes that must
+ *    outlive the handle. The library owns only host-side metadata.
+ *  - A handle is used by one thread at a time; distinct handles may be used
+ *    concurrently.
+ */
+#ifndef HY_H
+#define HY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hy_problem hy_problem; /* opaque, library-owned host object */
+
+typedef enum {
+  HY_OK = 0,
+  HY_ERR_ARG = 1,    /* invalid argument or configuration                    */
+  HY_ERR_NOMEM = 2,  /* workspace too small or host allocation failed         */
+  HY_ERR_HIP = 3,    /* a HIP runtime call failed                             */
+  HY_ERR_STATE = 4,  /* a non-finite value or rho <= 0 was seen on the device */
+  HY_ERR_BUDGET = 5  /* reserved for callers that enforce a memory budget     */
+} hy_status;
+
+enum { HY_BC_PERIODIC = 0, HY_BC_OUTFLOW = 1 };
+enum { HY_PLM = 0, HY_PPM4 = 1 };
+enum { HY_FP64 = 0, HY_MIXED = 1 };
+
+/* Problem definition (Sec. 2 mesh and boundaries; Sec. 3 algorithms).
+ *  n[3]        global interior cells (nx, ny, nz), each >= 1.
+ *  block[3]    MeshBlock interior size; must divide n and be >= the ghost
+ *              depth (2 for PLM, 3 for PPM4).
+ *  lo[3],hi[3] domain extents; dx_d = (hi_d - lo_d) / n_d > 0.
+ *  bc[3][2]    lower/upper boundary per axis: HY_BC_PERIODIC (both sides of
+ *              an axis must then be periodic) or HY_BC_OUTFLOW (zero-gradient
+ *              copy of the nearest interior cell).
+ *  gamma > 1; cfl in (0, 1].
+ *  recon       HY_PLM (van Leer limited slopes) or HY_PPM4 (Colella &
+ *              Woodward 1984 limiters), both on primitive variables.
+ *  precision   HY_FP64 (all arithmetic in FP64) or HY_MIXED (reconstruction
+ *              and the Riemann solve in FP32; cons-to-prim, flux divergence,
+ *              the RK accumulation and the time step in FP64; U stays FP64).
+ *  rho_floor, p_floor  floors applied to the primitive state only (U is
+ *              never modified by a floor); each firing is counted.          */
+typedef struct {
+  int32_t n[3];
+  int32_t block[3];
+  double lo[3], hi[3];
+  int32_t bc[3][2];
+  double gamma;
+  double cfl;
+  int32_t recon;
+  int32_t precision;
+  double rho_floor, p_floor;
+} hy_config;
+
+/* Device bytes one problem needs: two FP64 state registers of 5 x cells
+ * doubles each (the step-start state and the RK stage state) plus a 512-byte
+ * header. Returns 0 for an invalid configuration. */
+size_t hy_workspace_bytes(const hy_config* cfg);
+
+/* Create a problem in the caller's device workspace `dev_ws` (256-byte
+ * aligned, at least hy_workspace_bytes(cfg) bytes, on the current device).
+ * Writes the header synchronously. *out receives the handle. The state is
+ * undefined until hy_set_state. */
+hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_problem** out);
+
+/* Load the conserved state. U is the GLOBAL interior state as
+ * double[5][nz][ny][nx], x fastest, variables rho, Mx, My, Mz, E; a device
+ * pointer if on_device != 0, else a host pointer. The library scatters it into
+ * its MeshBlocks and computes the first time step from it (Eq. 3). Async for
+ * device input; host input is copied before return. Resets neither t nor the
+ * step count. */
+hy_status hy_set_state(hy_problem* p, const double* U, int on_device, void* hip_stream);
+
+/* Store the conserved state into U (same layout as hy_set_state). Waits for
+ * the stream, then reports HY_ERR_STATE if the device flagged a bad state. */
+hy_status hy_get_state(hy_problem* p, double* U, int on_device, void* hip_stream);
+
+/* Advance nsteps >= 0 full RK2 steps (async). Each step uses the time step
+ * computed on the device at the end of the previous one; the host never reads
+ * it back. */
+hy_status hy_advance(hy_problem* p, int32_t nsteps, void* hip_stream);
+
+/* Advance n problems together (async): problem q runs nsteps[q] steps. For
+ * every step index, one launch per RK stage covers the tiles of all problems
+ * still running that share a (reconstruction, precision) pair. Per-cell
+ * arithmetic is identical to hy_advance, so results are bitwise equal to
+ * running each problem alone. */
+hy_status hy_batch_advance(hy_problem* const* ps, const int32_t* nsteps, int32_t n,
+                           void* hip_stream);
+
+/* Wait for the problem's last stream, then read its time, the time step the
+ * next step will take, the steps taken and the floor hits (any pointer may be
+ * NULL). Returns HY_ERR_STATE if the device flagged a bad state. */
+hy_status hy_query(hy_problem* p, double* t, double* dt_next, int64_t* steps,
+                   int64_t* floor_hits);
+
+/* Set the simulation time (for resuming from a stored state). */
+hy_status hy_set_time(hy_problem* p, double t);
+
+/* Release the handle (not the workspace). Waits for the last stream. */
+hy_status hy_destroy(hy_problem* p);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* hy_last_error(void);
+
+/* ---------------- launch shapes and tuning -------------------------------
+ * The stage kernel works on x-y tiles of a MeshBlock, marching along z over
+ * chunks of kc planes. The compiled tile shapes (tx, ty) are listed by
+ * hy_num_variants/hy_variant_info; kc is any value >= 1. Results do not
+ * depend on the shape. */
+int32_t hy_num_variants(void);
+hy_status hy_variant_info(int32_t variant, int32_t* tx, int32_t* ty);
+hy_status hy_set_launch(hy_problem* p, int32_t variant, int32_t kc);
+hy_status hy_get_launch(const hy_problem* p, int32_t* variant, int32_t* kc);
+
+/* Time every compiled tile shape and a few z-chunk lengths on this problem's
+ * own state (stage-1 launches only, which leave the state unchanged), keep the
+ * fastest for this problem and cache it for its (block size, recon,
+ * precision) class. Synchronous. Returns the chosen shape in *variant/*kc
+ * (either may be NULL) and its time per stage in *us_per_stage. */
+hy_status hy_autotune(hy_problem* p, void* hip_stream, int32_t* variant, int32_t* kc,
+                      double* us_per_stage);
+
+/* ---------------- measurement helpers ------------------------------------- */
+/* Copy `bytes` (a multiple of 16) from device src to device dst with a plain
+ * streaming kernel (async). Used to calibrate HBM byte counters and measure
+ * achievable bandwidth. */
+hy_status hy_copy_probe(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+/* Record a HIP event pair around hy_advance launches: hy_advance_timed runs
+ * nsteps steps on the stream and returns the elapsed device time of the
+ * stage-1 and stage-2 launches separately (milliseconds), measured with HIP
+ * events recorded on that same stream. Synchronous. */
+hy_status hy_advance_timed(hy_problem* p, int32_t nsteps, void* hip_stream, double* ms_stage1,
+                           double* ms_stage2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HY_H */

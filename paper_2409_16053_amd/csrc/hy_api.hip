@@ -1,0 +1,520 @@
+// hy_api.hip -- host runtime behind the C ABI of include/hy.h.
+//
+// Owns host metadata only: the problem's workspace (two FP64 MeshBlockPack
+// registers and a 512-byte header) is provided by the caller. Launch planning
+// turns a set of problems into per-stage launch arguments: every problem's
+// MeshBlocks are cut into x-y tiles and z-chunks, and one launch per RK
+// stage covers the tiles of all problems that share a compiled kernel
+// (the paper's MeshBlockPack, Sec. 2, generalised to many problems).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "hy.h"
+#include "hy_internal.h"
+#include "hy_launch.h"
+
+using namespace hy;
+
+struct hy_problem {
+  hy_config cfg;
+  int ng;
+  int nblk[3];
+  int64_t ncell;
+  char* ws;
+  size_t ws_bytes;
+  DevProblem* dp;      // descriptor in device memory
+  DevCounters* dc;     // counters in device memory
+  DevProblem hp;       // host copy of the descriptor
+  int64_t steps;
+  int variant;
+  int kc;
+  hipStream_t last;
+  int device;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+hy_status fail(hy_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HY_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(HY_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr unsigned long long kInf = 0x7FF0000000000000ull;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int ghost_depth(int recon) { return recon == HY_PPM4 ? 3 : 2; }
+
+bool validate(const hy_config* c, std::string& msg) {
+  if (!c) { msg = "config is NULL"; return false; }
+  if (c->recon != HY_PLM && c->recon != HY_PPM4) { msg = "recon must be HY_PLM or HY_PPM4"; return false; }
+  if (c->precision != HY_FP64 && c->precision != HY_MIXED) { msg = "precision must be HY_FP64 or HY_MIXED"; return false; }
+  const int ng = ghost_depth(c->recon);
+  for (int d = 0; d < 3; ++d) {
+    if (c->n[d] < 1 || c->block[d] < 1) { msg = "n and block must be >= 1"; return false; }
+    if (c->n[d] % c->block[d]) { msg = "block must divide n on every axis"; return false; }
+    if (c->block[d] < ng) { msg = "block must be >= the ghost depth (2 PLM, 3 PPM4)"; return false; }
+    if (!(c->hi[d] > c->lo[d]) || !std::isfinite(c->hi[d] - c->lo[d])) { msg = "need hi > lo"; return false; }
+    for (int s = 0; s < 2; ++s)
+      if (c->bc[d][s] != HY_BC_PERIODIC && c->bc[d][s] != HY_BC_OUTFLOW) { msg = "bad boundary code"; return false; }
+    if ((c->bc[d][0] == HY_BC_PERIODIC) != (c->bc[d][1] == HY_BC_PERIODIC)) {
+      msg = "periodic boundaries must be paired on an axis";
+      return false;
+    }
+  }
+  if (!(c->gamma > 1.0) || !std::isfinite(c->gamma)) { msg = "gamma must be > 1"; return false; }
+  if (!(c->cfl > 0.0 && c->cfl <= 1.0)) { msg = "cfl must be in (0, 1]"; return false; }
+  if (!(c->rho_floor >= 0.0) || !(c->p_floor >= 0.0) || !std::isfinite(c->rho_floor) ||
+      !std::isfinite(c->p_floor)) {
+    msg = "floors must be finite and >= 0";
+    return false;
+  }
+  const double cells = (double)c->n[0] * c->n[1] * c->n[2];
+  if (cells * 5.0 * 8.0 * 2.0 > 4.0e12) { msg = "mesh too large"; return false; }
+  const double blk = (double)c->block[0] * c->block[1] * c->block[2] * 5.0;
+  if (blk > 2.0e9) { msg = "MeshBlock too large"; return false; }
+  return true;
+}
+
+size_t reg_bytes(const hy_config* c) {
+  return align256((size_t)c->n[0] * c->n[1] * c->n[2] * 5 * sizeof(double));
+}
+
+// Tuned launch shapes per (block size, recon, precision).
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> g_tune;
+
+void default_launch(const hy_problem* p, int* variant, int* kc) {
+  const int bx = p->cfg.block[0], bz = p->cfg.block[2];
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(bx, p->cfg.block[1], bz, p->cfg.recon, p->cfg.precision));
+    if (it != g_tune.end()) {
+      *variant = it->second.first;
+      *kc = it->second.second;
+      return;
+    }
+  }
+  // x tile as wide as the block allows (full 64-lane rows), else narrower
+  int v = 3;  // 16 x 16
+  for (int i = 0; i < num_stage_variants(); ++i) {
+    int tx, ty;
+    stage_variant_shape(i, &tx, &ty);
+    if (bx % tx == 0) { v = i; break; }
+  }
+  int tx, ty;
+  stage_variant_shape(v, &tx, &ty);
+  const int64_t cols = (int64_t)((bx + tx - 1) / tx) * ((p->cfg.block[1] + ty - 1) / ty);
+  const int64_t nb = (int64_t)p->nblk[0] * p->nblk[1] * p->nblk[2];
+  int k = bz;
+  while (k > 8 && nb * cols * ((bz + k - 1) / k) < 2048) k = (k + 1) / 2;
+  *variant = v;
+  *kc = k;
+}
+
+struct Plan {
+  int variant, recon, prec;
+  std::vector<int> idx;  // problems in this launch group
+};
+
+hy_status check_batch(hy_problem* const* ps, const int32_t* nsteps, int32_t n) {
+  if (n < 0 || (n > 0 && (!ps || !nsteps))) return fail(HY_ERR_ARG, "bad batch arguments");
+  for (int q = 0; q < n; ++q) {
+    if (!ps[q]) return fail(HY_ERR_ARG, "NULL problem in batch");
+    if (nsteps[q] < 0) return fail(HY_ERR_ARG, "nsteps must be >= 0");
+    for (int r = 0; r < q; ++r)
+      if (ps[r] == ps[q]) return fail(HY_ERR_ARG, "a problem appears twice in the batch");
+    if (ps[q]->device != ps[0]->device) return fail(HY_ERR_ARG, "problems on different devices");
+  }
+  return HY_OK;
+}
+
+std::vector<Plan> make_plans(hy_problem* const* ps, int32_t n) {
+  std::vector<Plan> plans;
+  for (int q = 0; q < n; ++q) {
+    const int rc = ps[q]->cfg.recon, pr = ps[q]->cfg.precision;
+    Plan* pl = nullptr;
+    for (auto& x : plans)
+      if (x.recon == rc && x.prec == pr) pl = &x;
+    if (!pl) {
+      plans.push_back(Plan{ps[q]->variant, rc, pr, {}});
+      pl = &plans.back();
+    }
+    pl->idx.push_back(q);
+  }
+  // the group's tile shape: that of its largest problem
+  for (auto& pl : plans) {
+    int64_t best = -1;
+    for (int q : pl.idx)
+      if (ps[q]->ncell > best) { best = ps[q]->ncell; pl.variant = ps[q]->variant; }
+  }
+  return plans;
+}
+
+hy_status launch_group(hy_problem* const* ps, const std::vector<int>& act, const Plan& pl,
+                       int stage, const std::vector<int64_t>& step_of, int flags, hipStream_t s) {
+  int tx, ty;
+  stage_variant_shape(pl.variant, &tx, &ty);
+  for (size_t c0 = 0; c0 < act.size(); c0 += kMaxBatch) {
+    StageArgs a;
+    std::memset(&a, 0, sizeof a);
+    int64_t tiles = 0;
+    const size_t c1 = std::min(act.size(), c0 + (size_t)kMaxBatch);
+    for (size_t c = c0; c < c1; ++c) {
+      const int q = act[c];
+      const hy_problem* p = ps[q];
+      BatchEntry& e = a.e[a.nprob++];
+      e.p = p->dp;
+      e.tile0 = (int32_t)tiles;
+      e.ntx = (p->cfg.block[0] + tx - 1) / tx;
+      e.nty = (p->cfg.block[1] + ty - 1) / ty;
+      e.kc = std::max(1, std::min(p->kc, p->cfg.block[2]));
+      e.ntz = (p->cfg.block[2] + e.kc - 1) / e.kc;
+      e.parity = (int32_t)(step_of[q] & 1);
+      e.flags = flags;
+      tiles += (int64_t)p->nblk[0] * p->nblk[1] * p->nblk[2] * e.ntx * e.nty * e.ntz;
+    }
+    if (tiles > 0x7fffffff) return fail(HY_ERR_ARG, "too many tiles in one launch");
+    a.ntiles = (int32_t)tiles;
+    if (tiles == 0) continue;
+    HY_HIP(launch_stage(pl.variant, pl.recon, pl.prec, stage, a, (int)tiles, s));
+  }
+  return HY_OK;
+}
+
+// Enqueue nsteps[q] steps of every problem; optional events around stages.
+hy_status run_batch(hy_problem* const* ps, const int32_t* nsteps, int32_t n, hipStream_t s,
+                    std::vector<hipEvent_t>* ev, int flags) {
+  hy_status st = check_batch(ps, nsteps, n);
+  if (st != HY_OK) return st;
+  if (n == 0) return HY_OK;
+  int dev;
+  HY_HIP(hipGetDevice(&dev));
+  if (dev != ps[0]->device) return fail(HY_ERR_ARG, "current device differs from the problems' device");
+  const std::vector<Plan> plans = make_plans(ps, n);
+  int32_t maxs = 0;
+  for (int q = 0; q < n; ++q) maxs = std::max(maxs, nsteps[q]);
+  std::vector<int64_t> step_of(n);
+  for (int q = 0; q < n; ++q) step_of[q] = ps[q]->steps;
+  size_t evi = 0;
+  if (ev) HY_HIP(hipEventRecord((*ev)[evi++], s));
+  for (int32_t k = 0; k < maxs; ++k) {
+    for (int stage = 1; stage <= 2; ++stage) {
+      for (const Plan& pl : plans) {
+        std::vector<int> act;
+        for (int q : pl.idx)
+          if (nsteps[q] > k) act.push_back(q);
+        st = launch_group(ps, act, pl, stage, step_of, flags, s);
+        if (st != HY_OK) return st;
+      }
+      if (ev) HY_HIP(hipEventRecord((*ev)[evi++], s));
+    }
+    for (int q = 0; q < n; ++q)
+      if (nsteps[q] > k) ++step_of[q];
+  }
+  for (int q = 0; q < n; ++q) {
+    ps[q]->steps = step_of[q];
+    ps[q]->last = s;
+  }
+  return HY_OK;
+}
+
+hy_status read_counters(hy_problem* p, DevCounters* c) {
+  HY_HIP(hipStreamSynchronize(p->last));
+  HY_HIP(hipMemcpy(c, p->dc, sizeof *c, hipMemcpyDeviceToHost));
+  return HY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hy_workspace_bytes(const hy_config* cfg) {
+  std::string msg;
+  if (!validate(cfg, msg)) {
+    g_err = msg;
+    return 0;
+  }
+  return (size_t)kHeaderBytes + 2 * reg_bytes(cfg);
+}
+
+hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_problem** out) {
+  std::string msg;
+  if (!out) return fail(HY_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!validate(cfg, msg)) return fail(HY_ERR_ARG, msg);
+  if (!dev_ws) return fail(HY_ERR_ARG, "workspace is NULL");
+  if (((uintptr_t)dev_ws) & 255) return fail(HY_ERR_ARG, "workspace must be 256-byte aligned");
+  const size_t need = hy_workspace_bytes(cfg);
+  if (ws_bytes < need) return fail(HY_ERR_NOMEM, "workspace smaller than hy_workspace_bytes()");
+  int dev;
+  HY_HIP(hipGetDevice(&dev));
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, dev_ws) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+      attr.device != dev) {
+    (void)hipGetLastError();
+    return fail(HY_ERR_ARG, "workspace is not device memory of the current device");
+  }
+  hy_problem* p = new (std::nothrow) hy_problem();
+  if (!p) return fail(HY_ERR_NOMEM, "host allocation failed");
+  p->cfg = *cfg;
+  p->ng = ghost_depth(cfg->recon);
+  for (int d = 0; d < 3; ++d) p->nblk[d] = cfg->n[d] / cfg->block[d];
+  p->ncell = (int64_t)cfg->n[0] * cfg->n[1] * cfg->n[2];
+  p->ws = (char*)dev_ws;
+  p->ws_bytes = ws_bytes;
+  p->dp = (DevProblem*)p->ws;
+  p->dc = (DevCounters*)(p->ws + sizeof(DevProblem));
+  p->device = dev;
+  p->last = nullptr;
+  p->steps = 0;
+
+  DevProblem& h = p->hp;
+  std::memset(&h, 0, sizeof h);
+  h.U = (double*)(p->ws + kHeaderBytes);
+  h.V = (double*)(p->ws + kHeaderBytes + reg_bytes(cfg));
+  h.dtmin = p->dc->dtmin;
+  h.time = &p->dc->time;
+  h.floor_hits = &p->dc->floor_hits;
+  h.err = &p->dc->err;
+  h.bx = cfg->block[0];
+  h.by = cfg->block[1];
+  h.bz = cfg->block[2];
+  h.nbx = p->nblk[0];
+  h.nby = p->nblk[1];
+  h.nbz = p->nblk[2];
+  for (int d = 0; d < 3; ++d) {
+    h.periodic[d] = cfg->bc[d][0] == HY_BC_PERIODIC;
+    h.dx[d] = (cfg->hi[d] - cfg->lo[d]) / cfg->n[d];
+  }
+  h.nblocks = p->nblk[0] * p->nblk[1] * p->nblk[2];
+  h.vstride = (int64_t)h.bx * h.by * h.bz;
+  h.bstride = 5 * h.vstride;
+  h.gamma = cfg->gamma;
+  h.cfl = cfg->cfl;
+  h.rho_floor = cfg->rho_floor;
+  h.p_floor = cfg->p_floor;
+
+  unsigned char hdr[kHeaderBytes];
+  std::memset(hdr, 0, sizeof hdr);
+  std::memcpy(hdr, &h, sizeof h);
+  DevCounters c;
+  std::memset(&c, 0, sizeof c);
+  c.dtmin[0] = c.dtmin[1] = kInf;
+  std::memcpy(hdr + sizeof(DevProblem), &c, sizeof c);
+  if (hipMemcpy(p->ws, hdr, sizeof hdr, hipMemcpyHostToDevice) != hipSuccess) {
+    delete p;
+    return fail(HY_ERR_HIP, "header upload failed");
+  }
+  default_launch(p, &p->variant, &p->kc);
+  *out = p;
+  return HY_OK;
+}
+
+hy_status hy_set_state(hy_problem* p, const double* U, int on_device, void* stream) {
+  if (!p || !U) return fail(HY_ERR_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const double* src = U;
+  const size_t bytes = (size_t)p->ncell * 5 * sizeof(double);
+  if (!on_device) {
+    HY_HIP(hipMemcpyAsync(p->hp.V, U, bytes, hipMemcpyHostToDevice, s));
+    src = p->hp.V;
+  }
+  HY_HIP(launch_scatter(p->dp, src, p->hp.U, p->ncell * 5, 1, s));
+  const int slot = (int)(p->steps & 1);
+  HY_HIP(launch_reset(p->dp, slot, 1, s));
+  HY_HIP(launch_dt(p->dp, p->ncell, slot, 1, s));
+  if (!on_device) HY_HIP(hipStreamSynchronize(s));
+  p->last = s;
+  return HY_OK;
+}
+
+hy_status hy_get_state(hy_problem* p, double* U, int on_device, void* stream) {
+  if (!p || !U) return fail(HY_ERR_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = (size_t)p->ncell * 5 * sizeof(double);
+  if (on_device) {
+    HY_HIP(launch_scatter(p->dp, p->hp.U, U, p->ncell * 5, 0, s));
+  } else {
+    HY_HIP(launch_scatter(p->dp, p->hp.U, p->hp.V, p->ncell * 5, 0, s));
+    HY_HIP(hipMemcpyAsync(U, p->hp.V, bytes, hipMemcpyDeviceToHost, s));
+  }
+  p->last = s;
+  DevCounters c;
+  hy_status st = read_counters(p, &c);
+  if (st != HY_OK) return st;
+  if (c.err) return fail(HY_ERR_STATE, "non-finite state or rho <= 0 seen on the device");
+  return HY_OK;
+}
+
+hy_status hy_advance(hy_problem* p, int32_t nsteps, void* stream) {
+  if (!p) return fail(HY_ERR_ARG, "NULL problem");
+  return run_batch(&p, &nsteps, 1, (hipStream_t)stream, nullptr, 1);
+}
+
+hy_status hy_batch_advance(hy_problem* const* ps, const int32_t* nsteps, int32_t n, void* stream) {
+  return run_batch(ps, nsteps, n, (hipStream_t)stream, nullptr, 1);
+}
+
+hy_status hy_query(hy_problem* p, double* t, double* dt_next, int64_t* steps, int64_t* floor_hits) {
+  if (!p) return fail(HY_ERR_ARG, "NULL problem");
+  DevCounters c;
+  hy_status st = read_counters(p, &c);
+  if (st != HY_OK) return st;
+  if (t) *t = c.time;
+  if (dt_next) {
+    double m;
+    std::memcpy(&m, &c.dtmin[p->steps & 1], sizeof m);
+    *dt_next = p->cfg.cfl * m;
+  }
+  if (steps) *steps = p->steps;
+  if (floor_hits) *floor_hits = (int64_t)c.floor_hits;
+  if (c.err) return fail(HY_ERR_STATE, "non-finite state or rho <= 0 seen on the device");
+  return HY_OK;
+}
+
+hy_status hy_set_time(hy_problem* p, double t) {
+  if (!p || !std::isfinite(t)) return fail(HY_ERR_ARG, "bad argument");
+  HY_HIP(hipStreamSynchronize(p->last));
+  HY_HIP(hipMemcpy(&p->dc->time, &t, sizeof t, hipMemcpyHostToDevice));
+  return HY_OK;
+}
+
+hy_status hy_destroy(hy_problem* p) {
+  if (!p) return HY_OK;
+  hipError_t e = hipStreamSynchronize(p->last);
+  delete p;
+  if (e != hipSuccess) return fail(HY_ERR_HIP, hipGetErrorString(e));
+  return HY_OK;
+}
+
+const char* hy_last_error(void) { return g_err.c_str(); }
+
+int32_t hy_num_variants(void) { return num_stage_variants(); }
+
+hy_status hy_variant_info(int32_t v, int32_t* tx, int32_t* ty) {
+  if (v < 0 || v >= num_stage_variants() || !tx || !ty) return fail(HY_ERR_ARG, "bad variant");
+  int a, b;
+  stage_variant_shape(v, &a, &b);
+  *tx = a;
+  *ty = b;
+  return HY_OK;
+}
+
+hy_status hy_set_launch(hy_problem* p, int32_t variant, int32_t kc) {
+  if (!p || variant < 0 || variant >= num_stage_variants() || kc < 1)
+    return fail(HY_ERR_ARG, "bad launch shape");
+  p->variant = variant;
+  p->kc = std::min(kc, p->cfg.block[2]);
+  return HY_OK;
+}
+
+hy_status hy_get_launch(const hy_problem* p, int32_t* variant, int32_t* kc) {
+  if (!p) return fail(HY_ERR_ARG, "NULL problem");
+  if (variant) *variant = p->variant;
+  if (kc) *kc = p->kc;
+  return HY_OK;
+}
+
+hy_status hy_autotune(hy_problem* p, void* stream, int32_t* variant, int32_t* kc, double* us) {
+  if (!p) return fail(HY_ERR_ARG, "NULL problem");
+  hipStream_t s = (hipStream_t)stream;
+  const int bz = p->cfg.block[2];
+  std::vector<int> kcs;
+  for (int k : {bz, bz / 2, bz / 4, 32, 16, 8})
+    if (k >= 4 && k <= bz && std::find(kcs.begin(), kcs.end(), k) == kcs.end()) kcs.push_back(k);
+  if (kcs.empty()) kcs.push_back(bz);
+  hipEvent_t e0, e1;
+  HY_HIP(hipEventCreate(&e0));
+  HY_HIP(hipEventCreate(&e1));
+  const int save_v = p->variant, save_k = p->kc;
+  float best = 1e30f;
+  int bv = save_v, bk = save_k;
+  std::vector<int64_t> step_of{p->steps};
+  std::vector<int> act{0};
+  hy_problem* ps[1] = {p};
+  hy_status st = HY_OK;
+  for (int v = 0; v < num_stage_variants() && st == HY_OK; ++v) {
+    for (int k : kcs) {
+      p->variant = v;
+      p->kc = k;
+      Plan pl{v, p->cfg.recon, p->cfg.precision, {0}};
+      st = launch_group(ps, act, pl, 1, step_of, 0, s);  // warm-up
+      if (st != HY_OK) break;
+      if (hipEventRecord(e0, s) != hipSuccess) { st = fail(HY_ERR_HIP, "event record"); break; }
+      for (int r = 0; r < 3 && st == HY_OK; ++r) st = launch_group(ps, act, pl, 1, step_of, 0, s);
+      if (st != HY_OK) break;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        st = fail(HY_ERR_HIP, "event sync");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; bv = v; bk = k; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != HY_OK) {
+    p->variant = save_v;
+    p->kc = save_k;
+    return st;
+  }
+  p->variant = bv;
+  p->kc = bk;
+  p->last = s;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(p->cfg.block[0], p->cfg.block[1], p->cfg.block[2], p->cfg.recon,
+                           p->cfg.precision)] = {bv, bk};
+  }
+  if (variant) *variant = bv;
+  if (kc) *kc = bk;
+  if (us) *us = best * 1000.0 / 3.0;
+  return HY_OK;
+}
+
+hy_status hy_copy_probe(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src || (bytes & 15) || (((uintptr_t)dst | (uintptr_t)src) & 15))
+    return fail(HY_ERR_ARG, "copy probe needs 16-byte aligned pointers and sizes");
+  HY_HIP(launch_copy(dst, src, bytes, (hipStream_t)stream));
+  return HY_OK;
+}
+
+hy_status hy_advance_timed(hy_problem* p, int32_t nsteps, void* stream, double* ms1, double* ms2) {
+  if (!p || nsteps < 0) return fail(HY_ERR_ARG, "bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<hipEvent_t> ev(2 * (size_t)nsteps + 1);
+  for (auto& e : ev) HY_HIP(hipEventCreate(&e));
+  hy_status st = run_batch(&p, &nsteps, 1, s, &ev, 1);
+  double a = 0, b = 0;
+  if (st == HY_OK && hipEventSynchronize(ev.back()) == hipSuccess) {
+    for (int k = 0; k < nsteps; ++k) {
+      float x = 0, y = 0;
+      (void)hipEventElapsedTime(&x, ev[2 * k], ev[2 * k + 1]);
+      (void)hipEventElapsedTime(&y, ev[2 * k + 1], ev[2 * k + 2]);
+      a += x;
+      b += y;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (ms1) *ms1 = a;
+  if (ms2) *ms2 = b;
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,772 @@
+// hy_kernels.hip -- gfx950 kernels of the 3D Newtonian adiabatic hydro update.
+//
+// One fused kernel per RK stage performs the whole reconstruct-solve-advance
+// sequence of Stone et al. 2024 (arXiv:2409.16053), Sec. 3: ghost zones,
+// cons-to-prim (Sec. 3.1, Eq. 4), PLM or PPM4 reconstruction on primitives,
+// HLLC fluxes in x, y and z, the flux divergence and the SSP-RK2 stage
+// update; stage 2 also reduces the CFL time step of Sec. 3, Eq. 3.
+//
+// Work decomposition. A workgroup owns an x-y tile (TX x TY columns) of one
+// MeshBlock and marches along z through a chunk of planes. Each owned column
+// keeps its z stencil (primitives, slopes or PPM edge values, and the lower
+// z-face flux) in registers, so z neighbours cost no memory traffic. For the
+// current plane the primitives of the tile and of its x/y ghost zones sit in
+// LDS; all x- and y-faces of the plane are spread evenly over the threads,
+// each computing both one-sided reconstructions and the HLLC flux of its face
+// and leaving it in LDS for the divergence. Global memory is only touched by
+// x-contiguous rows: one new plane of U per step of the march, the ghost rows
+// of the tile, and the output row.
+//
+// Ghost zones are not stored: a tile's ghost cells are read straight from
+// the neighbouring MeshBlock's interior (same level, same device), or from the
+// nearest interior cell at an outflow boundary, which is exactly what the
+// paper's ghost-zone copy would have put there (Sec. 2, "Boundary conditions").
+//
+// Precision. T = double or float is the type of reconstruction and the
+// Riemann solve. Cons-to-prim, the flux divergence, the RK update and the time
+// step are always FP64. The library is built with -ffp-contract=off so every
+// instantiation performs identical per-cell arithmetic; FMAs are written out
+// where wanted.
+#include "hy_internal.h"
+
+namespace hy {
+
+constexpr unsigned long long kInfBits = 0x7FF0000000000000ull;
+
+// ---------------------------------------------------------------- helpers
+template <typename T>
+__device__ __forceinline__ T rcp(T x) {
+  return T(1) / x;
+}
+
+// XCD-aware remap: the dispatcher hands workgroup w to XCD w % 8. Give each
+// XCD a contiguous run of logical tiles so that tiles sharing ghost rows share
+// an L2.
+__device__ __forceinline__ int xcd_remap(int w, int G) {
+  const int q = G >> 3, r = G & 7;
+  const int x = w & 7, s = w >> 3;
+  return x * q + (x < r ? x : r) + s;
+}
+
+// ---------------------------------------------------------- reconstruction
+// PLM: van Leer harmonic-mean slope of a cell from its neighbours (faces are
+// w0 -/+ slope/2).
+template <typename T>
+__device__ __forceinline__ T plm_slope(T wm, T w0, T wp) {
+  const T dl = w0 - wm, dr = wp - w0;
+  const T prod = dl * dr;
+  const T s = (T(2) * prod) / (dl + dr);
+  return prod > T(0) ? s : T(0);
+}
+
+// PPM4 (Colella & Woodward 1984): monotonised central slope, Eq. 1.8.
+template <typename T>
+__device__ __forceinline__ T ppm_dm(T wm, T w0, T wp) {
+  const T dl = w0 - wm, dr = wp - w0;
+  const T da = T(0.5) * (wp - wm);
+  T m = fabs(da);
+  m = fmin(m, T(2) * fabs(dl));
+  m = fmin(m, T(2) * fabs(dr));
+  return dl * dr > T(0) ? copysign(m, da) : T(0);
+}
+
+// PPM4 interface value between cells c and c+1, Eq. 1.6 on a uniform mesh.
+template <typename T>
+__device__ __forceinline__ T ppm_iface(T wc, T wc1, T dmc, T dmc1) {
+  return (wc + T(0.5) * (wc1 - wc)) - (dmc1 - dmc) * T(1.0 / 6.0);
+}
+
+// PPM4 monotonicity constraints, Eq. 1.10: edge values (aL, aR) of a cell
+// with average a.
+template <typename T>
+__device__ __forceinline__ void ppm_mono(T a, T& aL, T& aR) {
+  const bool ext = (aR - a) * (a - aL) <= T(0);
+  const T d = aR - aL;
+  const T m6 = d * (a - T(0.5) * (aL + aR));
+  const T d26 = (d * d) * T(1.0 / 6.0);
+  const bool over_l = m6 > d26;
+  const bool over_r = !over_l && (-d26 > m6);
+  const T nL = over_l ? T(3) * a - T(2) * aR : aL;
+  const T nR = over_r ? T(3) * a - T(2) * aL : aR;
+  aL = ext ? a : nL;
+  aR = ext ? a : nR;
+}
+
+// --------------------------------------------------------------- HLLC
+// Toro-Spruce-Speares HLLC with pressure-based (PVRS) wave speeds (Toro's
+// textbook, Ch. 10). States are [rho, u_n, u_t1, u_t2, u_g]; p = (gamma-1) u_g.
+// Flux out: [mass, normal momentum, t1 momentum, t2 momentum, energy].
+// Selection: S_L >= 0 -> F_L; S* >= 0 -> F*_L; S_R > 0 -> F*_R; else F_R.
+template <typename T>
+struct Gas {
+  T gamma, gm1, cq;  // cq = (gamma + 1) / (2 gamma)
+};
+
+template <typename T>
+__device__ __forceinline__ void hllc(const Gas<T>& g, T rl, T ul, T vl, T wl, T ugl, T rr,
+                                     T ur, T vr, T wr, T ugr, T f[5]) {
+  const T pl = g.gm1 * ugl, pr = g.gm1 * ugr;
+  const T el = ugl + T(0.5) * rl * ((ul * ul + vl * vl) + wl * wl);
+  const T er = ugr + T(0.5) * rr * ((ur * ur + vr * vr) + wr * wr);
+  const T il = rcp(rl), ir = rcp(rr);
+  const T al = sqrt(g.gamma * pl * il), ar = sqrt(g.gamma * pr * ir);
+
+  const T ppv = T(0.5) * (pl + pr) - T(0.5) * (ur - ul) * (T(0.5) * (rl + rr)) * (T(0.5) * (al + ar));
+  const T ps = fmax(ppv, T(0));
+  const T ql = ps <= pl ? T(1) : sqrt(T(1) + g.cq * (ps * rcp(pl) - T(1)));
+  const T qr = ps <= pr ? T(1) : sqrt(T(1) + g.cq * (ps * rcp(pr) - T(1)));
+  const T sl = ul - al * ql, sr = ur + ar * qr;
+  const T ml = rl * (sl - ul), mr = rr * (sr - ur);
+  const T sst = ((pr - pl) + ml * ul - mr * ur) / (ml - mr);
+
+  const bool c1 = sl >= T(0), c2 = sst >= T(0), c3 = sr > T(0);
+  const bool useL = c1 || c2;                 // side K of the selected flux
+  const bool direct = c1 || (!c2 && !c3);     // F_K itself, no star state
+
+  const T rk = useL ? rl : rr, uk = useL ? ul : ur, vk = useL ? vl : vr;
+  const T wk = useL ? wl : wr, pk = useL ? pl : pr, ek = useL ? el : er;
+  const T sk = useL ? sl : sr, mk = useL ? ml : mr, ik = useL ? il : ir;
+
+  const T mu = rk * uk;
+  const T fk0 = mu, fk1 = mu * uk + pk, fk2 = mu * vk, fk3 = mu * wk, fk4 = uk * (ek + pk);
+
+  const T fac = mk / (sk - sst);
+  const T us0 = fac, us1 = fac * sst, us2 = fac * vk, us3 = fac * wk;
+  const T us4 = fac * (ek * ik + (sst - uk) * (sst + pk / mk));
+  f[0] = direct ? fk0 : fk0 + sk * (us0 - rk);
+  f[1] = direct ? fk1 : fk1 + sk * (us1 - mu);
+  f[2] = direct ? fk2 : fk2 + sk * (us2 - rk * vk);
+  f[3] = direct ? fk3 : fk3 + sk * (us3 - rk * wk);
+  f[4] = direct ? fk4 : fk4 + sk * (us4 - ek);
+}
+
+// --------------------------------------------------------- cons -> prim
+// Sec. 3.1, Eq. 4: rho, v = M/rho, u_g = E - |M|^2/(2 rho). Floors act on the
+// primitives only. `hit` counts a floor firing, `bad` a non-finite state or
+// rho <= 0. Always FP64 (the kinetic-energy cancellation needs it).
+struct Floors {
+  double rho, ug;
+};
+
+__device__ __forceinline__ void c2p(const Floors& fl, const double u[5], double w[5], int& hit,
+                                    int& bad) {
+  bool b = !(u[0] > 0.0);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) b = b || !isfinite(u[q]);
+  bad |= b ? 1 : 0;
+  double rho = u[0];
+  const bool fr = rho < fl.rho;
+  rho = fr ? fl.rho : rho;
+  const double irho = 1.0 / rho;
+  const double ke2 = (u[1] * u[1] + u[2] * u[2]) + u[3] * u[3];
+  double ug = u[4] - (0.5 * ke2) * irho;
+  const bool fu = ug < fl.ug;
+  ug = fu ? fl.ug : ug;
+  hit += (fr || fu) ? 1 : 0;
+  w[0] = rho;
+  w[1] = u[1] * irho;
+  w[2] = u[2] * irho;
+  w[3] = u[3] * irho;
+  w[4] = ug;
+}
+
+// dx_d / (|v_d| + c_s) minimised over d for one cell (Sec. 3, Eq. 3).
+__device__ __forceinline__ double cell_dt(const Floors& fl, double gamma, double gm1,
+                                          const double dx[3], const double u[5]) {
+  double w[5];
+  int h = 0, b = 0;
+  c2p(fl, u, w, h, b);
+  const double cs = sqrt(gamma * (gm1 * w[4]) / w[0]);
+  double m = dx[0] / (fabs(w[1]) + cs);
+  m = fmin(m, dx[1] / (fabs(w[2]) + cs));
+  m = fmin(m, dx[2] / (fabs(w[3]) + cs));
+  return m;
+}
+
+// ------------------------------------------------------- block geometry
+struct Geo {
+  int bx, by, bz;
+  int m;       // this tile's block
+  int nb[6];   // neighbour block per face (-x,+x,-y,+y,-z,+z); -1 = outflow
+  int64_t bstride, vstride;
+};
+
+__device__ __forceinline__ void geo_init(Geo& g, const DevProblem& P, int m) {
+  g.bx = P.bx;
+  g.by = P.by;
+  g.bz = P.bz;
+  g.m = m;
+  g.bstride = P.bstride;
+  g.vstride = P.vstride;
+  const int nbx = P.nbx, nby = P.nby, nbz = P.nbz;
+  const int mx = m % nbx, t = m / nbx, my = t % nby, mz = t / nby;
+  const int sxy = nbx * nby;
+  g.nb[0] = mx > 0 ? m - 1 : (P.periodic[0] ? m + (nbx - 1) : -1);
+  g.nb[1] = mx < nbx - 1 ? m + 1 : (P.periodic[0] ? m - (nbx - 1) : -1);
+  g.nb[2] = my > 0 ? m - nbx : (P.periodic[1] ? m + (nby - 1) * nbx : -1);
+  g.nb[3] = my < nby - 1 ? m + nbx : (P.periodic[1] ? m - (nby - 1) * nbx : -1);
+  g.nb[4] = mz > 0 ? m - sxy : (P.periodic[2] ? m + (nbz - 1) * sxy : -1);
+  g.nb[5] = mz < nbz - 1 ? m + sxy : (P.periodic[2] ? m - (nbz - 1) * sxy : -1);
+}
+
+// Offset (in doubles, variable 0) of cell (i,j,k) given in this block's local
+// coordinates, of which at most one may lie outside the block by <= its size:
+// the ghost-zone rule of periodic / neighbour copies and outflow clamping.
+__device__ __forceinline__ int64_t ghost_off(const Geo& g, int i, int j, int k) {
+  int mb = g.m;
+  if (i < 0) {
+    if (g.nb[0] >= 0) { mb = g.nb[0]; i += g.bx; } else { i = 0; }
+  } else if (i >= g.bx) {
+    if (g.nb[1] >= 0) { mb = g.nb[1]; i -= g.bx; } else { i = g.bx - 1; }
+  }
+  if (j < 0) {
+    if (g.nb[2] >= 0) { mb = g.nb[2]; j += g.by; } else { j = 0; }
+  } else if (j >= g.by) {
+    if (g.nb[3] >= 0) { mb = g.nb[3]; j -= g.by; } else { j = g.by - 1; }
+  }
+  if (k < 0) {
+    if (g.nb[4] >= 0) { mb = g.nb[4]; k += g.bz; } else { k = 0; }
+  } else if (k >= g.bz) {
+    if (g.nb[5] >= 0) { mb = g.nb[5]; k -= g.bz; } else { k = g.bz - 1; }
+  }
+  return (int64_t)mb * g.bstride + ((int64_t)k * g.by + j) * g.bx + i;
+}
+
+__device__ __forceinline__ void load5(const double* __restrict__ base, int64_t off, int64_t vs,
+                                      double u[5]) {
+#pragma unroll
+  for (int q = 0; q < 5; ++q) u[q] = __builtin_nontemporal_load(base + off + q * vs);
+}
+
+__device__ __forceinline__ void load5c(const double* __restrict__ base, int64_t off, int64_t vs,
+                                       double u[5]) {
+#pragma unroll
+  for (int q = 0; q < 5; ++q) u[q] = base[off + q * vs];
+}
+
+// --------------------------------------------------------- z-march queues
+// Per-column register state of the z sweep. PLM: the face k+1/2 needs cells
+// k-1..k+2; PPM4: cells k-2..k+3.
+template <int RECON, typename T>
+struct ZQueue;
+
+template <typename T>
+struct ZQueue<0, T> {       // PLM
+  T w0[5], w1[5];           // primitives at k and k+1
+  T s0[5];                  // limited slope at k
+  double fm[5];             // z-flux through the face k-1/2
+};
+
+template <typename T>
+struct ZQueue<1, T> {       // PPM4
+  T w0[5], w1[5], w2[5];    // primitives at k, k+1, k+2
+  T dm1[5];                 // limited slope at k+1
+  T a1[5];                  // interface value at k+1/2
+  T ar0[5];                 // monotonised right edge of cell k
+  double fm[5];
+};
+
+template <typename T>
+__device__ __forceinline__ void zflux(const Gas<T>& g, const T wl[5], const T wr[5], double f[5]) {
+  // z-normal: (n, t1, t2) = (vz, vx, vy)
+  T h[5];
+  hllc(g, wl[0], wl[3], wl[1], wl[2], wl[4], wr[0], wr[3], wr[1], wr[2], wr[4], h);
+  f[0] = (double)h[0];
+  f[3] = (double)h[1];
+  f[1] = (double)h[2];
+  f[2] = (double)h[3];
+  f[4] = (double)h[4];
+}
+
+// -------------------------------------------------------------- the stage
+// Stage 1: V = U + dt L(U).   Stage 2: U = U/2 + V/2 + dt L(V)/2, then the
+// minimum of dx_d/lambda_d over the new U for the next time step.
+template <int RECON, typename T, int TX, int TY, int STAGE>
+__global__ void __launch_bounds__(TX* TY) k_stage(const StageArgs a) {
+  constexpr int NG = RECON == 0 ? 2 : 3;
+  constexpr int NT = TX * TY;
+  constexpr int SX = TX + 2 * NG;
+  constexpr int SY = TY + 2 * NG;
+  constexpr int PLANE = SX * SY;
+  constexpr int NXF = (TX + 1) * TY;
+  constexpr int NYF = TX * (TY + 1);
+  constexpr int NF = NXF + NYF;
+  constexpr int NHX = 2 * NG * TY;
+  constexpr int NH = NHX + 2 * NG * TX;
+  constexpr int NWAVE = NT / kWave;
+  static_assert(NT % kWave == 0, "tile must be whole wavefronts");
+
+  __shared__ T sW[5 * PLANE];
+  __shared__ T sF[5 * NF];
+  __shared__ unsigned long long sRed[NWAVE];
+
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+
+  for (int L = xcd_remap(blockIdx.x, gridDim.x); L < a.ntiles; L += gridDim.x) {
+    // ---- locate problem, block and tile (uniform across the workgroup)
+    int q = 0;
+    while (q + 1 < a.nprob && a.e[q + 1].tile0 <= L) ++q;
+    const BatchEntry E = a.e[q];
+    const DevProblem& P = *E.p;
+    const int loc = L - E.tile0;
+    const int per_blk = E.ntx * E.nty * E.ntz;
+    const int m = loc / per_blk;
+    int r = loc - m * per_blk;
+    const int tzi = r / (E.ntx * E.nty);
+    r -= tzi * (E.ntx * E.nty);
+    const int tyi = r / E.ntx;
+    const int txi = r - tyi * E.ntx;
+
+    Geo geo;
+    geo_init(geo, P, m);
+    const int i0 = txi * TX, j0 = tyi * TY, k0 = tzi * E.kc;
+    const int nxv = min(TX, geo.bx - i0), nyv = min(TY, geo.by - j0);
+    const int kend = min(k0 + E.kc, geo.bz);
+    const bool own = tx < nxv && ty < nyv;
+    const int gi = i0 + tx, gj = j0 + ty;  // owned column, block-local
+
+    const double* __restrict__ Sin = STAGE == 1 ? P.U : P.V;
+    double* __restrict__ Out = STAGE == 1 ? P.V : P.U;
+    const int64_t vs = geo.vstride;
+
+    const double gamma = P.gamma, gm1 = gamma - 1.0;
+    const Gas<T> gas{T(gamma), T(gm1), T((gamma + 1.0) / (2.0 * gamma))};
+    const Floors fl{P.rho_floor, P.p_floor / gm1};
+    const double dt = P.cfl * __longlong_as_double((long long)P.dtmin[E.parity]);
+    const double idx = 1.0 / P.dx[0], idy = 1.0 / P.dx[1], idz = 1.0 / P.dx[2];
+    const bool count = (E.flags & 1) != 0;
+
+    if (STAGE == 1 && loc == 0 && tid == 0) P.dtmin[E.parity ^ 1] = kInfBits;
+
+    int hits = 0, bad = 0;
+    double mydt = __longlong_as_double((long long)kInfBits);
+
+    // column offset of the owned cell in plane k (valid for 0 <= k < bz)
+    const int64_t col0 = (int64_t)m * geo.bstride + (int64_t)gj * geo.bx + gi;
+    const int64_t pstride = (int64_t)geo.by * geo.bx;
+
+    auto col_load = [&](int k, double u[5]) {
+      const int64_t off = (k >= 0 && k < geo.bz) ? col0 + k * pstride : ghost_off(geo, gi, gj, k);
+      load5c(Sin, off, vs, u);
+    };
+    auto to_prim = [&](const double u[5], T w[5], int k) {
+      double wd[5];
+      int h = 0, b = 0;
+      c2p(fl, u, wd, h, b);
+      if (k >= k0 && k < kend) {  // interior cell of this tile: count once
+        hits += h;
+        bad |= b;
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) w[v] = (T)wd[v];
+    };
+
+    ZQueue<RECON, T> zq;
+    if (own) {
+      if constexpr (RECON == 0) {
+        double u[5];
+        T wa[5], wb[5], wc[5], wd[5];
+        col_load(k0 - 2, u); to_prim(u, wa, k0 - 2);
+        col_load(k0 - 1, u); to_prim(u, wb, k0 - 1);
+        col_load(k0, u); to_prim(u, wc, k0);
+        col_load(k0 + 1, u); to_prim(u, wd, k0 + 1);
+        T wl[5], wr[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const T sb = plm_slope(wa[v], wb[v], wc[v]);
+          const T sc = plm_slope(wb[v], wc[v], wd[v]);
+          wl[v] = wb[v] + T(0.5) * sb;
+          wr[v] = wc[v] - T(0.5) * sc;
+          zq.w0[v] = wc[v];
+          zq.w1[v] = wd[v];
+          zq.s0[v] = sc;
+        }
+        zflux(gas, wl, wr, zq.fm);
+      } else {
+        double u[5];
+        T c[6][5];
+#pragma unroll
+        for (int o = 0; o < 6; ++o) {
+          col_load(k0 - 3 + o, u);
+          to_prim(u, c[o], k0 - 3 + o);
+        }
+        T wl[5], wr[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          // slopes at k0-2 .. k0+1 (cells c[1..4])
+          const T d1 = ppm_dm(c[0][v], c[1][v], c[2][v]);
+          const T d2 = ppm_dm(c[1][v], c[2][v], c[3][v]);
+          const T d3 = ppm_dm(c[2][v], c[3][v], c[4][v]);
+          const T d4 = ppm_dm(c[3][v], c[4][v], c[5][v]);
+          const T am = ppm_iface(c[1][v], c[2][v], d1, d2);  // k0-3/2
+          const T a0 = ppm_iface(c[2][v], c[3][v], d2, d3);  // k0-1/2
+          const T ap = ppm_iface(c[3][v], c[4][v], d3, d4);  // k0+1/2
+          T l1 = am, r1 = a0;                                 // cell k0-1
+          ppm_mono(c[2][v], l1, r1);
+          T l2 = a0, r2 = ap;                                 // cell k0
+          ppm_mono(c[3][v], l2, r2);
+          wl[v] = r1;
+          wr[v] = l2;
+          zq.w0[v] = c[3][v];
+          zq.w1[v] = c[4][v];
+          zq.w2[v] = c[5][v];
+          zq.dm1[v] = d4;
+          zq.a1[v] = ap;
+          zq.ar0[v] = r2;
+        }
+        zflux(gas, wl, wr, zq.fm);
+      }
+    }
+
+    for (int k = k0; k < kend; ++k) {
+      // ---- next plane of the owned column (latency overlaps the face work)
+      double un[5];
+      if (own) col_load(k + (RECON == 0 ? 2 : 3), un);
+
+      // ---- primitives of plane k into LDS: owned cells from the queue,
+      //      ghost cells of the tile from neighbours / boundary conditions
+      if (own) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sW[v * PLANE + (ty + NG) * SX + (tx + NG)] = zq.w0[v];
+      }
+      for (int h = tid; h < NH; h += NT) {
+        int li, lj;
+        bool ok;
+        if (h < NHX) {
+          const int side = h / (NG * TY);
+          const int rem = h - side * (NG * TY);
+          lj = rem / NG;
+          const int g = rem - lj * NG;
+          li = side ? nxv + g : g - NG;
+          ok = lj < nyv;
+        } else {
+          const int hh = h - NHX;
+          const int side = hh / (NG * TX);
+          const int rem = hh - side * (NG * TX);
+          const int g = rem / TX;
+          li = rem - g * TX;
+          lj = side ? nyv + g : g - NG;
+          ok = li < nxv;
+        }
+        if (ok) {
+          double u[5], wd[5];
+          load5c(Sin, ghost_off(geo, i0 + li, j0 + lj, k), vs, u);
+          int hh = 0, bb = 0;
+          c2p(fl, u, wd, hh, bb);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) sW[v * PLANE + (lj + NG) * SX + (li + NG)] = (T)wd[v];
+        }
+      }
+      __syncthreads();
+
+      // ---- x- and y-faces of plane k, spread over all threads
+      for (int w = tid; w < NF; w += NT) {
+        int fi, fj, dir, base, stride;
+        bool ok;
+        if (w < NXF) {
+          fj = w / (TX + 1);
+          fi = w - fj * (TX + 1);
+          dir = 0;
+          ok = fi <= nxv && fj < nyv;
+          base = (fj + NG) * SX + (fi + NG);
+          stride = 1;
+        } else {
+          const int ww = w - NXF;
+          fj = ww / TX;
+          fi = ww - fj * TX;
+          dir = 1;
+          ok = fi < nxv && fj <= nyv;
+          base = (fj + NG) * SX + (fi + NG);
+          stride = SX;
+        }
+        if (ok) {
+          T wl[5], wr[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            const T* s = sW + v * PLANE + base;
+            if constexpr (RECON == 0) {
+              const T c0 = s[-2 * stride], c1 = s[-stride], c2 = s[0], c3 = s[stride];
+              wl[v] = c1 + T(0.5) * plm_slope(c0, c1, c2);
+              wr[v] = c2 - T(0.5) * plm_slope(c1, c2, c3);
+            } else {
+              const T c0 = s[-3 * stride], c1 = s[-2 * stride], c2 = s[-stride];
+              const T c3 = s[0], c4 = s[stride], c5 = s[2 * stride];
+              const T d1 = ppm_dm(c0, c1, c2), d2 = ppm_dm(c1, c2, c3);
+              const T d3 = ppm_dm(c2, c3, c4), d4 = ppm_dm(c3, c4, c5);
+              const T am = ppm_iface(c1, c2, d1, d2);
+              const T a0 = ppm_iface(c2, c3, d2, d3);
+              const T ap = ppm_iface(c3, c4, d3, d4);
+              T l1 = am, r1 = a0;
+              ppm_mono(c2, l1, r1);
+              T l2 = a0, r2 = ap;
+              ppm_mono(c3, l2, r2);
+              wl[v] = r1;
+              wr[v] = l2;
+            }
+          }
+          // rotate: x-face (n,t1,t2) = (vx,vy,vz); y-face = (vy,vz,vx)
+          const T nl = dir ? wl[2] : wl[1], al = dir ? wl[3] : wl[2], bl = dir ? wl[1] : wl[3];
+          const T nr = dir ? wr[2] : wr[1], ar = dir ? wr[3] : wr[2], br = dir ? wr[1] : wr[3];
+          T f[5];
+          hllc(gas, wl[0], nl, al, bl, wl[4], wr[0], nr, ar, br, wr[4], f);
+          sF[0 * NF + w] = f[0];
+          sF[1 * NF + w] = dir ? f[3] : f[1];
+          sF[2 * NF + w] = dir ? f[1] : f[2];
+          sF[3 * NF + w] = dir ? f[2] : f[3];
+          sF[4 * NF + w] = f[4];
+        }
+      }
+
+      // ---- z-face k+1/2 of the owned column (registers only)
+      double fz[5];
+      if (own) {
+        if constexpr (RECON == 0) {
+          T w2[5];
+          to_prim(un, w2, k + 2);
+          T wl[5], wr[5], s1[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            s1[v] = plm_slope(zq.w0[v], zq.w1[v], w2[v]);
+            wl[v] = zq.w0[v] + T(0.5) * zq.s0[v];
+            wr[v] = zq.w1[v] - T(0.5) * s1[v];
+          }
+          zflux(gas, wl, wr, fz);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            zq.w0[v] = zq.w1[v];
+            zq.w1[v] = w2[v];
+            zq.s0[v] = s1[v];
+          }
+        } else {
+          T w3[5];
+          to_prim(un, w3, k + 3);
+          T wl[5], wr[5], d2[5], a2[5], r1[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            d2[v] = ppm_dm(zq.w1[v], zq.w2[v], w3[v]);                 // slope at k+2
+            a2[v] = ppm_iface(zq.w1[v], zq.w2[v], zq.dm1[v], d2[v]);    // k+3/2
+            T l1 = zq.a1[v];
+            r1[v] = a2[v];
+            ppm_mono(zq.w1[v], l1, r1[v]);                              // cell k+1
+            wl[v] = zq.ar0[v];
+            wr[v] = l1;
+          }
+          zflux(gas, wl, wr, fz);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            zq.w0[v] = zq.w1[v];
+            zq.w1[v] = zq.w2[v];
+            zq.w2[v] = w3[v];
+            zq.dm1[v] = d2[v];
+            zq.a1[v] = a2[v];
+            zq.ar0[v] = r1[v];
+          }
+        }
+      }
+      __syncthreads();
+
+      // ---- divergence and RK stage update of the owned cell
+      if (own) {
+        const int64_t off = col0 + k * pstride;
+        const int wx = ty * (TX + 1) + tx;
+        const int wy = NXF + ty * TX + tx;
+        double uc[5], un0[5];
+        load5c(Sin, off, vs, uc);
+        if (STAGE == 2) load5(P.U, off, vs, un0);
+        double unew[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const double fxm = (double)sF[v * NF + wx], fxp = (double)sF[v * NF + wx + 1];
+          const double fym = (double)sF[v * NF + wy], fyp = (double)sF[v * NF + wy + TX];
+          double l = -(fxp - fxm) * idx;
+          l -= (fyp - fym) * idy;
+          l -= (fz[v] - zq.fm[v]) * idz;
+          if (STAGE == 1) {
+            unew[v] = uc[v] + dt * l;
+          } else {
+            unew[v] = (0.5 * un0[v] + 0.5 * uc[v]) + (0.5 * dt) * l;
+          }
+          zq.fm[v] = fz[v];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(unew[v], Out + off + v * vs);
+        if (STAGE == 2) mydt = fmin(mydt, cell_dt(fl, gamma, gm1, P.dx, unew));
+      }
+    }
+
+    // ---- per-tile reductions: floors, bad-state flag, time step
+    if (count) {
+      if (hits) atomicAdd(P.floor_hits, (unsigned long long)hits);
+      if (bad) atomicOr(P.err, 1u);
+    }
+    if (STAGE == 2) {
+      unsigned long long b = (unsigned long long)__double_as_longlong(mydt);
+#pragma unroll
+      for (int s = kWave / 2; s > 0; s >>= 1) {
+        const unsigned long long o = __shfl_xor(b, s, kWave);
+        b = o < b ? o : b;
+      }
+      if ((tid & (kWave - 1)) == 0) sRed[tid / kWave] = b;
+      __syncthreads();
+      if (tid == 0) {
+        unsigned long long mn = sRed[0];
+        for (int wv = 1; wv < NWAVE; ++wv) mn = sRed[wv] < mn ? sRed[wv] : mn;
+        atomicMin(P.dtmin + (E.parity ^ 1), mn);
+        if (loc == 0) *P.time = *P.time + dt;
+      }
+    }
+    __syncthreads();  // LDS reuse by the next tile of this workgroup
+  }
+}
+
+// ------------------------------------------------------------ small kernels
+// Time step of a stored state into dtmin[slot] (after k_reset_dt).
+__global__ void __launch_bounds__(256) k_dt(const DevProblem* __restrict__ Pp, int slot, int flags) {
+  const DevProblem& P = *Pp;
+  const int64_t ncell = (int64_t)P.nblocks * P.vstride;
+  const double gamma = P.gamma, gm1 = gamma - 1.0;
+  const Floors fl{P.rho_floor, P.p_floor / gm1};
+  double mydt = __longlong_as_double((long long)kInfBits);
+  int bad = 0;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = c / P.vstride, rr = c - m * P.vstride;
+    double u[5];
+    load5c(P.U, m * P.bstride + rr, P.vstride, u);
+    double w[5];
+    int h = 0;
+    c2p(fl, u, w, h, bad);
+    mydt = fmin(mydt, cell_dt(fl, gamma, gm1, P.dx, u));
+  }
+  if ((flags & 1) && bad) atomicOr(P.err, 1u);
+  unsigned long long b = (unsigned long long)__double_as_longlong(mydt);
+  for (int s = kWave / 2; s > 0; s >>= 1) {
+    const unsigned long long o = __shfl_xor(b, s, kWave);
+    b = o < b ? o : b;
+  }
+  __shared__ unsigned long long red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long mn = red[0];
+    for (int w = 1; w < 4; ++w) mn = red[w] < mn ? red[w] : mn;
+    atomicMin(P.dtmin + slot, mn);
+  }
+}
+
+// Header fields set from the device (no memset nodes: safe under capture).
+// clear bit 0: error flag; bit 1: floor counter and time.
+__global__ void k_reset(const DevProblem* __restrict__ Pp, int slot, int clear) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const DevProblem& P = *Pp;
+    P.dtmin[slot] = kInfBits;
+    if (clear & 1) *P.err = 0u;
+    if (clear & 2) {
+      *P.floor_hits = 0ull;
+      *P.time = 0.0;
+    }
+  }
+}
+
+// Global [5][nz][ny][nx] <-> MeshBlockPack [m][5][bz][by][bx].
+__global__ void __launch_bounds__(256) k_scatter(const DevProblem* __restrict__ Pp,
+                                                 const double* __restrict__ src,
+                                                 double* __restrict__ dst, int to_blocks) {
+  const DevProblem& P = *Pp;
+  const int64_t nx = (int64_t)P.bx * P.nbx, ny = (int64_t)P.by * P.nby;
+  const int64_t nz = (int64_t)P.bz * P.nbz;
+  const int64_t n = 5 * nx * ny * nz;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int64_t t = g;
+    const int64_t i = t % nx; t /= nx;
+    const int64_t j = t % ny; t /= ny;
+    const int64_t k = t % nz;
+    const int64_t v = t / nz;
+    const int64_t m = (i / P.bx) + P.nbx * ((j / P.by) + P.nby * (k / P.bz));
+    const int64_t b = m * P.bstride + v * P.vstride +
+                      ((k % P.bz) * P.by + (j % P.by)) * P.bx + (i % P.bx);
+    if (to_blocks) dst[b] = src[g];
+    else dst[g] = src[b];
+  }
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Plain streaming copy (16 bytes per lane per iteration).
+__global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                              int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+// ------------------------------------------------------ dispatch tables
+// Compiled tile shapes (TX x TY threads); TX*TY must be a multiple of 64.
+#define HY_STAGE_SET(TX, TY)                                                              \
+  {TX, TY,                                                                                \
+   {{{(const void*)&k_stage<0, double, TX, TY, 1>, (const void*)&k_stage<0, double, TX, TY, 2>}, \
+     {(const void*)&k_stage<0, float, TX, TY, 1>, (const void*)&k_stage<0, float, TX, TY, 2>}},   \
+    {{(const void*)&k_stage<1, double, TX, TY, 1>, (const void*)&k_stage<1, double, TX, TY, 2>}, \
+     {(const void*)&k_stage<1, float, TX, TY, 1>, (const void*)&k_stage<1, float, TX, TY, 2>}}}}
+
+struct StageVariant {
+  int tx, ty;
+  const void* fn[2][2][2];  // [recon][precision][stage-1]
+};
+
+static const StageVariant kStageVariants[] = {
+    HY_STAGE_SET(64, 8), HY_STAGE_SET(32, 8), HY_STAGE_SET(64, 4), HY_STAGE_SET(16, 16),
+};
+
+int num_stage_variants() { return (int)(sizeof(kStageVariants) / sizeof(kStageVariants[0])); }
+
+void stage_variant_shape(int v, int* tx, int* ty) {
+  *tx = kStageVariants[v].tx;
+  *ty = kStageVariants[v].ty;
+}
+
+const void* stage_kernel(int v, int recon, int prec, int stage) {
+  return kStageVariants[v].fn[recon][prec][stage - 1];
+}
+
+hipError_t launch_stage(int v, int recon, int prec, int stage, const StageArgs& a, int grid,
+                        hipStream_t s) {
+  const StageVariant& sv = kStageVariants[v];
+  void* args[] = {(void*)&a};
+  return hipLaunchKernel(sv.fn[recon][prec][stage - 1], dim3(grid), dim3(sv.tx * sv.ty), args, 0, s);
+}
+
+hipError_t launch_reset(const DevProblem* p, int slot, int clear, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, p, slot, clear);
+  return hipGetLastError();
+}
+
+hipError_t launch_dt(const DevProblem* p, int64_t ncell, int slot, int flags, hipStream_t s) {
+  int64_t g = (ncell + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_dt, dim3((unsigned)g), dim3(256), 0, s, p, slot, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const DevProblem* p, const double* src, double* dst, int64_t n,
+                          int to_blocks, hipStream_t s) {
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)g), dim3(256), 0, s, p, src, dst, to_blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / 16);
+  int64_t g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)g), dim3(256), 0, s, (const u32x4*)src, (u32x4*)dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace hy

@@ -1,0 +1,16 @@
+// hy_launch.h -- host-side entry points of the kernels in hy_kernels.hip.
+#pragma once
+#include "hy_internal.h"
+
+namespace hy {
+int num_stage_variants();
+void stage_variant_shape(int v, int* tx, int* ty);
+const void* stage_kernel(int v, int recon, int prec, int stage);
+hipError_t launch_stage(int v, int recon, int prec, int stage, const StageArgs& a, int grid,
+                        hipStream_t s);
+hipError_t launch_reset(const DevProblem* p, int slot, int clear, hipStream_t s);
+hipError_t launch_dt(const DevProblem* p, int64_t ncell, int slot, int flags, hipStream_t s);
+hipError_t launch_scatter(const DevProblem* p, const double* src, double* dst, int64_t n,
+                          int to_blocks, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+}  // namespace hy

@@ -1,0 +1,266 @@
+"""Thin ctypes binding of the C ABI in ``include/hy.h`` (``libhy.so``).
+
+Argument marshalling only: every step of the hydro update runs in the gfx950
+kernels of the library. PyTorch provides device memory (each problem's
+workspace is a ``torch.uint8`` CUDA tensor owned here) and streams. There is
+no CPU fallback: if the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhy.so")
+
+HY_OK, HY_ERR_ARG, HY_ERR_NOMEM, HY_ERR_HIP, HY_ERR_STATE, HY_ERR_BUDGET = range(6)
+PERIODIC, OUTFLOW = 0, 1
+PLM, PPM4 = 0, 1
+FP64, MIXED = 0, 1
+
+# (name, argtypes, restype) of every entry point declared in include/hy.h
+_c = ctypes
+_vp = _c.c_void_p
+_dp = _c.POINTER(_c.c_double)
+
+
+class HyConfig(_c.Structure):
+    _fields_ = [
+        ("n", _c.c_int32 * 3),
+        ("block", _c.c_int32 * 3),
+        ("lo", _c.c_double * 3),
+        ("hi", _c.c_double * 3),
+        ("bc", (_c.c_int32 * 2) * 3),
+        ("gamma", _c.c_double),
+        ("cfl", _c.c_double),
+        ("recon", _c.c_int32),
+        ("precision", _c.c_int32),
+        ("rho_floor", _c.c_double),
+        ("p_floor", _c.c_double),
+    ]
+
+
+_CP = _c.POINTER(HyConfig)
+_i32p = _c.POINTER(_c.c_int32)
+_i64p = _c.POINTER(_c.c_int64)
+
+SIGNATURES = {
+    "hy_workspace_bytes": ([_CP], _c.c_size_t),
+    "hy_create": ([_CP, _vp, _c.c_size_t, _c.POINTER(_vp)], _c.c_int),
+    "hy_set_state": ([_vp, _vp, _c.c_int, _vp], _c.c_int),
+    "hy_get_state": ([_vp, _vp, _c.c_int, _vp], _c.c_int),
+    "hy_advance": ([_vp, _c.c_int32, _vp], _c.c_int),
+    "hy_batch_advance": ([_c.POINTER(_vp), _i32p, _c.c_int32, _vp], _c.c_int),
+    "hy_query": ([_vp, _dp, _dp, _i64p, _i64p], _c.c_int),
+    "hy_set_time": ([_vp, _c.c_double], _c.c_int),
+    "hy_destroy": ([_vp], _c.c_int),
+    "hy_last_error": ([], _c.c_char_p),
+    "hy_num_variants": ([], _c.c_int32),
+    "hy_variant_info": ([_c.c_int32, _i32p, _i32p], _c.c_int),
+    "hy_set_launch": ([_vp, _c.c_int32, _c.c_int32], _c.c_int),
+    "hy_get_launch": ([_vp, _i32p, _i32p], _c.c_int),
+    "hy_autotune": ([_vp, _vp, _i32p, _i32p, _dp], _c.c_int),
+    "hy_copy_probe": ([_vp, _vp, _c.c_size_t, _vp], _c.c_int),
+    "hy_advance_timed": ([_vp, _c.c_int32, _vp, _dp, _dp], _c.c_int),
+}
+
+_lib = None
+
+
+class HydroError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hy status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libhy.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2409_16053_amd.build` (or __graft_entry__.build())")
+        L = _c.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().hy_last_error().decode()
+
+
+def _check(st):
+    if st != HY_OK:
+        raise HydroError(st, last_error())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the hydro library needs a ROCm GPU; none is visible")
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _vp(s.cuda_stream)
+
+
+def make_config(pb) -> HyConfig:
+    """HyConfig from a ``problems.Problem``."""
+    c = HyConfig()
+    block = pb.block if pb.block is not None else pb.n
+    for d in range(3):
+        c.n[d] = int(pb.n[d])
+        c.block[d] = int(block[d])
+        c.lo[d] = float(pb.lo[d])
+        c.hi[d] = float(pb.hi[d])
+        c.bc[d][0] = int(pb.bc[d][0])
+        c.bc[d][1] = int(pb.bc[d][1])
+    c.gamma = float(pb.gamma)
+    c.cfl = float(pb.cfl)
+    c.recon = int(pb.recon)
+    c.precision = int(pb.precision)
+    c.rho_floor = float(pb.rho_floor)
+    c.p_floor = float(pb.p_floor)
+    return c
+
+
+def workspace_bytes(pb) -> int:
+    c = make_config(pb)
+    n = lib().hy_workspace_bytes(_c.byref(c))
+    if n == 0:
+        raise HydroError(HY_ERR_ARG, last_error())
+    return int(n)
+
+
+def variants():
+    out = []
+    for v in range(lib().hy_num_variants()):
+        tx, ty = _c.c_int32(), _c.c_int32()
+        _check(lib().hy_variant_info(v, _c.byref(tx), _c.byref(ty)))
+        out.append((tx.value, ty.value))
+    return out
+
+
+class Problem:
+    """One hydro problem resident on the GPU (state, counters, launch shape)."""
+
+    def __init__(self, pb, device=None):
+        torch = _torch()
+        self.pb = pb
+        self.cfg = make_config(pb)
+        self.nbytes = workspace_bytes(pb)
+        dev = torch.device("cuda" if device is None else device)
+        # 256-byte aligned workspace carved from a torch allocation
+        self._buf = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self._buf.data_ptr()
+        self._off = (-base) % 256
+        self.ws_ptr = base + self._off
+        self.device = dev
+        h = _vp()
+        with torch.cuda.device(dev):
+            _check(lib().hy_create(_c.byref(self.cfg), _vp(self.ws_ptr), self.nbytes, _c.byref(h)))
+        self.h = h
+        self.shape = (5, int(pb.n[2]), int(pb.n[1]), int(pb.n[0]))
+
+    # -- state ---------------------------------------------------------
+    def set_state(self, U=None, stream=None):
+        torch = _torch()
+        U = self.pb.U if U is None else U
+        if isinstance(U, torch.Tensor) and U.is_cuda:
+            t = U.to(torch.float64).contiguous()
+            assert tuple(t.shape) == self.shape
+            _check(lib().hy_set_state(self.h, _vp(t.data_ptr()), 1, _stream(stream)))
+            self._keep = t
+        else:
+            a = np.ascontiguousarray(U, dtype=np.float64)
+            assert a.shape == self.shape
+            _check(lib().hy_set_state(self.h, _vp(a.ctypes.data), 0, _stream(stream)))
+        return self
+
+    def get_state(self, device=False, stream=None):
+        torch = _torch()
+        if device:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+            _check(lib().hy_get_state(self.h, _vp(out.data_ptr()), 1, _stream(stream)))
+            return out
+        out = np.empty(self.shape, dtype=np.float64)
+        _check(lib().hy_get_state(self.h, _vp(out.ctypes.data), 0, _stream(stream)))
+        return out
+
+    def get_state_status(self, stream=None):
+        """(status, U) without raising on a device-flagged bad state."""
+        out = np.empty(self.shape, dtype=np.float64)
+        st = lib().hy_get_state(self.h, _vp(out.ctypes.data), 0, _stream(stream))
+        return st, out
+
+    # -- time stepping ---------------------------------------------------
+    def advance(self, nsteps, stream=None):
+        _check(lib().hy_advance(self.h, int(nsteps), _stream(stream)))
+        return self
+
+    def advance_timed(self, nsteps, stream=None):
+        a, b = _c.c_double(), _c.c_double()
+        _check(lib().hy_advance_timed(self.h, int(nsteps), _stream(stream), _c.byref(a), _c.byref(b)))
+        return a.value, b.value
+
+    def query(self, raise_on_state=True):
+        t, dt = _c.c_double(), _c.c_double()
+        steps, fh = _c.c_int64(), _c.c_int64()
+        st = lib().hy_query(self.h, _c.byref(t), _c.byref(dt), _c.byref(steps), _c.byref(fh))
+        if st != HY_OK and (raise_on_state or st != HY_ERR_STATE):
+            _check(st)
+        return dict(t=t.value, dt=dt.value, steps=steps.value, floor_hits=fh.value, status=st)
+
+    def set_time(self, t):
+        _check(lib().hy_set_time(self.h, float(t)))
+
+    # -- launch shape ------------------------------------------------------
+    def set_launch(self, variant, kc):
+        _check(lib().hy_set_launch(self.h, int(variant), int(kc)))
+
+    def get_launch(self):
+        v, k = _c.c_int32(), _c.c_int32()
+        _check(lib().hy_get_launch(self.h, _c.byref(v), _c.byref(k)))
+        return v.value, k.value
+
+    def autotune(self, stream=None):
+        v, k, us = _c.c_int32(), _c.c_int32(), _c.c_double()
+        _check(lib().hy_autotune(self.h, _stream(stream), _c.byref(v), _c.byref(k), _c.byref(us)))
+        return v.value, k.value, us.value
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().hy_destroy(self.h)
+            self.h = _vp()
+        self._buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_advance(problems, nsteps, stream=None):
+    """Advance several problems together (one launch per stage and kernel)."""
+    n = len(problems)
+    hs = (_vp * n)(*[p.h for p in problems])
+    if np.isscalar(nsteps):
+        nsteps = [int(nsteps)] * n
+    ns = (_c.c_int32 * n)(*[int(x) for x in nsteps])
+    _check(lib().hy_batch_advance(hs, ns, n, _stream(stream)))
+
+
+def copy_probe(dst, src, nbytes=None, stream=None):
+    """Plain device-to-device streaming copy with the library's probe kernel."""
+    nbytes = src.numel() * src.element_size() if nbytes is None else nbytes
+    _check(lib().hy_copy_probe(_vp(dst.data_ptr()), _vp(src.data_ptr()), int(nbytes), _stream(stream)))

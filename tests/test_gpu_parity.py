@@ -1,0 +1,258 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU reference solver.
+
+Both sides start from the same seeded state. The FP64 gate is the relative L1
+difference rel = sum|U_gpu - U_ref| / sum|U_ref| over all interior cells and
+the five conserved variables <= 1e-12 after the stated steps; elementwise,
+every conserved value must also agree to 1e-9 of that variable's largest
+magnitude, which bounds local divergence. Both sides evaluate the same
+formulas in FP64 with different rounding order (the GPU uses reciprocals and
+a different summation order), so differences start at ~1e-16 per operation.
+The mixed-precision path (FP32 reconstruction and Riemann solve) is gated at
+rel <= 1e-5 against the same FP64 reference.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_16053_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+FP64_REL = 1e-12
+FP64_ELEM = 1e-9
+MIXED_REL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def hy():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_16053_amd import hy as _hy
+    _hy.lib()
+    return _hy
+
+
+def rel_l1(a, b):
+    return float(np.abs(a - b).sum() / np.abs(b).sum())
+
+
+def elem_err(a, b):
+    scale = np.abs(b).reshape(5, -1).max(axis=1)
+    scale = np.where(scale > 0, scale, 1.0)
+    return float((np.abs(a - b).reshape(5, -1).max(axis=1) / scale).max())
+
+
+def run_gpu(hy, pb, steps, variant=None, kc=None):
+    g = hy.Problem(pb).set_state()
+    if variant is not None:
+        g.set_launch(variant, kc if kc is not None else pb.block[2])
+    g.advance(steps)
+    U = g.get_state()
+    q = g.query()
+    g.close()
+    return U, q
+
+
+def check_fp64(hy, pb, steps, label, **kw):
+    print(f"[{label}] n={pb.n} block={pb.block} recon={pb.recon} steps={steps}", flush=True)
+    U, q = run_gpu(hy, pb, steps, **kw)
+    ref = oracle.advance(pb, steps)
+    assert ref["status"] == 0
+    r = rel_l1(U, ref["U"])
+    e = elem_err(U, ref["U"])
+    print(f"[{label}] rel L1 {r:.3e}  elem {e:.3e}  t {q['t']:.15g}/{ref['t']:.15g} "
+          f"dt {q['dt']:.15g}/{ref['dt']:.15g} floors {q['floor_hits']}/{ref['floor_hits']}", flush=True)
+    assert r <= FP64_REL, r
+    assert e <= FP64_ELEM, e
+    assert abs(q["t"] - ref["t"]) <= 1e-13 * max(1.0, abs(ref["t"]))
+    assert abs(q["dt"] / ref["dt"] - 1.0) <= 1e-11
+    assert q["steps"] == steps
+    return U, q, ref
+
+
+# ------------------------------------------------------------ the workloads
+def test_eigenmode_32_fp64(hy):
+    pb, steps = P.workload_eigenmode_32()
+    check_fp64(hy, pb, steps, "eigenmode32")
+
+
+def test_turbulence_64_every_tile_shape(hy):
+    pb = P.turbulence(N=64, seed=1).with_(block=(32, 32, 32))
+    ref = oracle.advance(pb, 6)
+    outs = []
+    for v, (tx, ty) in enumerate(hy.variants()):
+        for kc in (32, 7):
+            U, q = run_gpu(hy, pb, 6, variant=v, kc=kc)
+            r = rel_l1(U, ref["U"])
+            print(f"[turb64 v{v} {tx}x{ty} kc{kc}] rel L1 {r:.3e} elem {elem_err(U, ref['U']):.3e}", flush=True)
+            assert r <= FP64_REL
+            outs.append(U)
+    for U in outs[1:]:
+        assert np.array_equal(U, outs[0]), "tile shape changed the result"
+
+
+def test_ragged_tiles_kh(hy):
+    # blocks of 48 x 24 x 20: every compiled tile shape leaves ragged tiles
+    pb = P.kelvin_helmholtz(n=(96, 48, 40), seed=5).with_(block=(48, 24, 20))
+    ref = oracle.advance(pb, 5)
+    outs = []
+    for v in range(len(hy.variants())):
+        U, _ = run_gpu(hy, pb, 5, variant=v, kc=6)
+        r = rel_l1(U, ref["U"])
+        print(f"[kh ragged v{v}] rel L1 {r:.3e}", flush=True)
+        assert r <= FP64_REL
+        outs.append(U)
+    for U in outs[1:]:
+        assert np.array_equal(U, outs[0])
+
+
+def test_kh_ppm4_64(hy):
+    pb = P.kelvin_helmholtz(N=64, seed=2).with_(block=(32, 32, 32), recon=P.PPM4)
+    check_fp64(hy, pb, 10, "kh64 ppm4")
+
+
+def test_kh_ppm4_128_blocks_64(hy):
+    # the 512^3 KH workload's layout at 128^3: 2^3 MeshBlocks of 64^3, PPM4
+    pb = P.kelvin_helmholtz(N=128, seed=2).with_(block=(64, 64, 64), recon=P.PPM4)
+    check_fp64(hy, pb, 10, "kh128 ppm4")
+
+
+def test_sedov_outflow(hy):
+    pb = P.sedov(N=32, seed=3).with_(block=(16, 16, 16))
+    check_fp64(hy, pb, 20, "sedov32")
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_sod_each_axis(hy, axis):
+    pb = P.sod(N=64, axis=axis, ntrans=8).with_(block=tuple(32 if d == axis else 4 for d in range(3)))
+    check_fp64(hy, pb, 25, f"sod axis {axis}")
+
+
+def test_single_block_periodic_wrap(hy):
+    # one MeshBlock per axis: every ghost zone wraps onto the block itself
+    pb = P.turbulence(N=24, seed=9, kmax=6).with_(block=(24, 24, 24), recon=P.PPM4)
+    check_fp64(hy, pb, 8, "turb24 single block ppm4")
+
+
+def test_mixed_boundaries(hy):
+    # periodic in x and z, outflow in y
+    pb = P.kelvin_helmholtz(n=(32, 32, 16), seed=4).with_(block=(16, 8, 8))
+    pb = pb.with_(bc=((P.PERIODIC, P.PERIODIC), (P.OUTFLOW, P.OUTFLOW), (P.PERIODIC, P.PERIODIC)))
+    check_fp64(hy, pb, 10, "kh mixed bc")
+
+
+# ------------------------------------------------------------ mixed precision
+@pytest.mark.parametrize("case", ["turb", "kh_ppm4", "sedov", "wave3"])
+def test_mixed_precision_vs_fp64_reference(hy, case):
+    if case == "turb":
+        pb, steps = P.turbulence(N=64, seed=1).with_(block=(32, 32, 32)), 20
+    elif case == "kh_ppm4":
+        pb, steps = P.kelvin_helmholtz(N=64, seed=2).with_(block=(32, 32, 32), recon=P.PPM4), 10
+    elif case == "sedov":
+        pb, steps = P.sedov(N=32, seed=3).with_(block=(16, 16, 16)), 50
+    else:
+        pb, steps = P.sound_wave(N=32, amp=1e-3).with_(block=(16, 16, 16)), 20
+    ref = oracle.advance(pb, steps)
+    U, q = run_gpu(hy, pb.with_(precision=P.MIXED), steps)
+    r = rel_l1(U, ref["U"])
+    print(f"[mixed {case}] rel L1 vs FP64 reference {r:.3e}", flush=True)
+    assert r <= MIXED_REL, r
+
+
+# ------------------------------------------------------------ invariants
+@pytest.mark.parametrize("recon", [P.PLM, P.PPM4])
+@pytest.mark.parametrize("prec", [P.FP64, P.MIXED])
+@pytest.mark.parametrize("bc", [P.PERIODIC, P.OUTFLOW])
+def test_uniform_state_bitwise(hy, recon, prec, bc):
+    pb = P.uniform(n=(32, 24, 16), rho=1.3, v=(0.3, -0.2, 0.4), p=0.8, bc=bc)
+    pb = pb.with_(block=(16, 8, 8), recon=recon, precision=prec)
+    U, q = run_gpu(hy, pb, 4)
+    assert np.array_equal(U, pb.U)
+    assert q["floor_hits"] == 0
+
+
+def test_conservation_periodic(hy):
+    pb = P.turbulence(N=64, seed=1).with_(block=(16, 16, 16))
+    U, _ = run_gpu(hy, pb, 20)
+    eps = np.finfo(np.float64).eps
+    bound = 4 * eps * np.sqrt(pb.cells * 40)
+    for v in range(5):
+        scale = np.abs(pb.U[v]).sum() + np.abs(U[v]).sum()
+        assert abs(U[v].sum() - pb.U[v].sum()) <= bound * scale, v
+
+
+# ------------------------------------------------------------ API behaviour
+def test_checkpoint_resume_bitwise(hy):
+    pb = P.kelvin_helmholtz(N=32, seed=6).with_(block=(16, 16, 16))
+    a = hy.Problem(pb).set_state()
+    a.advance(10)
+    Ua, qa = a.get_state(), a.query()
+    b = hy.Problem(pb).set_state()
+    b.advance(5)
+    Um, qm = b.get_state(), b.query()
+    c = hy.Problem(pb).set_state(Um)
+    c.set_time(qm["t"])
+    c.advance(5)
+    Uc, qc = c.get_state(), c.query()
+    assert np.array_equal(Ua, Uc)
+    assert qa["t"] == qc["t"] and qa["dt"] == qc["dt"]
+    for g in (a, b, c):
+        g.close()
+
+
+def test_device_state_roundtrip(hy):
+    import torch
+    pb = P.sedov(N=32, seed=8).with_(block=(16, 16, 16))
+    g = hy.Problem(pb).set_state(torch.from_numpy(pb.U).cuda())
+    assert np.array_equal(g.get_state(device=True).cpu().numpy(), pb.U)
+    assert np.array_equal(g.get_state(), pb.U)
+    g.close()
+
+
+def test_bad_state_reported(hy):
+    pb = P.uniform(n=(16, 16, 16), p=1.0).with_(block=(8, 8, 8))
+    U = pb.U.copy()
+    U[0, 3, 4, 5] = np.nan
+    g = hy.Problem(pb).set_state(U)
+    g.advance(1)
+    st, _ = g.get_state_status()
+    assert st == hy.HY_ERR_STATE
+    U = pb.U.copy()
+    U[0, 1, 2, 3] = -1.0
+    g2 = hy.Problem(pb).set_state(U)
+    assert g2.query(raise_on_state=False)["status"] == hy.HY_ERR_STATE
+    g.close()
+    g2.close()
+
+
+def test_rejects_bad_configs(hy):
+    pb = P.uniform(n=(16, 16, 16))
+    for bad in (dict(block=(5, 16, 16)), dict(block=(1, 16, 16)), dict(gamma=1.0), dict(cfl=0.0),
+                dict(bc=((0, 1), (0, 0), (0, 0))), dict(recon=7)):
+        with pytest.raises(hy.HydroError) as ei:
+            hy.Problem(pb.with_(**bad))
+        assert ei.value.status == hy.HY_ERR_ARG
+
+
+# ------------------------------------------------------------ batching
+def test_batch_equals_alone_bitwise(hy):
+    pbs = [
+        P.sedov(N=32, seed=11).with_(block=(16, 16, 16)),
+        P.sedov(N=48, seed=12).with_(block=(48, 48, 48), precision=P.MIXED),
+        P.kelvin_helmholtz(N=32, seed=13).with_(block=(32, 32, 32), recon=P.PPM4),
+        P.turbulence(N=32, seed=14, kmax=8).with_(block=(16, 16, 16)),
+        P.sedov(N=32, seed=15).with_(block=(32, 32, 32), precision=P.MIXED),
+    ]
+    steps = [7, 5, 9, 3, 6]
+    alone = []
+    for pb, n in zip(pbs, steps):
+        U, q = run_gpu(hy, pb, n)
+        alone.append((U, q))
+    gs = [hy.Problem(pb).set_state() for pb in pbs]
+    hy.batch_advance(gs, steps)
+    for g, (U, q), n in zip(gs, alone, steps):
+        Ub, qb = g.get_state(), g.query()
+        assert np.array_equal(Ub, U)
+        assert qb["t"] == q["t"] and qb["dt"] == q["dt"] and qb["steps"] == n
+        g.close()
