@@ -1,0 +1,184 @@
+"""Throughput of the 3D hydro update on one MI355X.
+
+Workload: 256^3 periodic turbulence (seeded solenoidal velocity field, k^-5/3
+over k = 1..16, rms Mach 0.5) in 64 MeshBlocks of 64^3, PLM + HLLC, SSP-RK2,
+CFL 0.3. One "step" is one full RK2 time step through the whole hot path
+(ghost zones, cons-to-prim, reconstruction, HLLC in x/y/z, divergence, both
+RK stages, CFL reduction). `value` is cell-updates/s in FP64 (interior cells x
+steps / wall seconds, state resident in HBM); the mixed-precision path is
+timed the same way and reported beside it.
+
+Prints one JSON line. Also:
+  --copy-probe BYTES   run the library's plain copy kernel on a buffer of BYTES
+                       (used to calibrate rocprofv3 byte counters)
+  --skip-cpu           skip the CPU reference-solver baseline
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s 3D PLM+HLLC RK2, FP64 vs mixed; % HBM roofline; p99 latency"
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per interior cell and launch: stage 1 reads U and
+# writes V (2 x 40 B); stage 2 reads V and U and writes U (3 x 40 B)
+BYTES_STAGE = {1: 80.0, 2: 120.0}
+COUNTERS = os.path.join(ROOT, "profiles", "stage_turbulence256_counters.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("hy_kernels.hip", "hy_internal.h"):
+        with open(os.path.join(ROOT, "paper_2409_16053_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--N", type=int, default=256)
+    ap.add_argument("--block", type=int, default=64)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--skip-mixed", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(halo exchange across GPUs is not implemented).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2409_16053_amd import hy
+    from paper_2409_16053_amd import problems as P
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    if args.copy_probe:
+        nb = args.copy_probe // 16 * 16
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            hy.copy_probe(dst, src, nb)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 x {nb} bytes")
+
+    log(f"building workload: turbulence {args.N}^3 in blocks of {args.block}^3")
+    pb, _ = P.workload_turbulence_256(N=args.N, block=args.block)
+    cells = pb.cells
+
+    def run(precision):
+        g = hy.Problem(pb.with_(precision=precision)).set_state()
+        g.advance(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms1, ms2 = g.advance_timed(args.steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        q = g.query()
+        U = g.get_state()
+        launch = g.get_launch()
+        g.close()
+        sec = t1 - t0
+        return dict(sec=sec, ms1=ms1, ms2=ms2, q=q, U=U, launch=launch)
+
+    log("timing FP64")
+    r64 = run(P.FP64)
+    value = cells * args.steps / r64["sec"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r64["sec"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"turbulence {args.N}^3 periodic, {(args.N // args.block) ** 3} MeshBlocks of "
+                        f"{args.block}^3, PLM+HLLC, SSP-RK2, CFL 0.3, rho=1 P=1, rms Mach 0.5, seed 1",
+            "cells": cells,
+            "tile_variant": list(hy.variants()[r64["launch"][0]]) + [r64["launch"][1]],
+        },
+    }
+
+    # live per-kernel times from HIP events on the launch stream
+    a1 = r64["ms1"] / args.steps * 1e-3
+    a2 = r64["ms2"] / args.steps * 1e-3
+    dom = 2 if a2 >= a1 else 1
+    avg = a2 if dom == 2 else a1
+    achieved = BYTES_STAGE[dom] * cells / avg / 1e9
+    traffic = None
+    if os.path.exists(COUNTERS):
+        c = json.load(open(COUNTERS))
+        if c.get("kernel_source_hash") == kernel_source_hash() and c.get("cells") == cells:
+            traffic = c.get(f"stage{dom}_hbm_bytes_per_launch")
+    out["roofline"] = {
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "kernel": f"k_stage stage {dom} (FP64, PLM)",
+        "avg_launch_ms": avg * 1e3,
+        "other_stage_avg_launch_ms": (a1 if dom == 2 else a2) * 1e3,
+        "bytes_per_cell": BYTES_STAGE[dom],
+    }
+
+    if not args.skip_mixed:
+        log("timing mixed precision")
+        rmx = run(P.MIXED)
+        rel = float(np.abs(rmx["U"] - r64["U"]).sum() / np.abs(r64["U"]).sum())
+        out["mixed"] = {
+            "value": cells * args.steps / rmx["sec"],
+            "ms_per_step": 1e3 * rmx["sec"] / args.steps,
+            "stage1_ms": rmx["ms1"] / args.steps,
+            "stage2_ms": rmx["ms2"] / args.steps,
+            "rel_l1_vs_fp64_gpu": rel,
+            "dtype": "f32 reconstruct/Riemann, f64 state/divergence/dt",
+        }
+
+    if not args.skip_cpu:
+        import oracle
+        oracle.build(force=False)
+        nsteps = args.cpu_steps
+        log(f"timing the CPU reference solver ({nsteps} steps on the full mesh)")
+        t0 = time.perf_counter()
+        r = oracle.advance(pb, nsteps)
+        t1 = time.perf_counter()
+        out["cpu_baseline"] = {
+            "value": cells * nsteps / (t1 - t0),
+            "unit": "cell-updates/s",
+            "cores": oracle.get_threads(),
+            "kind": "oracle",
+            "sample": f"{nsteps} RK2 steps of the same {args.N}^3 turbulence state (FP64, PLM+HLLC), "
+                      f"{t1 - t0:.1f} s wall",
+        }
+        assert r["status"] == 0
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

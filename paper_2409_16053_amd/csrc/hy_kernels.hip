@@ -34,10 +34,21 @@ namespace hy {
 constexpr unsigned long long kInfBits = 0x7FF0000000000000ull;
 
 // ---------------------------------------------------------------- helpers
-template <typename T>
-__device__ __forceinline__ T rcp(T x) {
-  return T(1) / x;
+// Reciprocal and square root. FP64: the hardware reciprocal estimate refined
+// by two Newton-Raphson steps (error squared each step) to full double
+// precision; callers only form x * rcp(y) where y != 0 on every selected
+// branch. FP32 (mixed path, reconstruction and Riemann solve only): the
+// native 1-ulp instructions.
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
 }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rsqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // XCD-aware remap: the dispatcher hands workgroup w to XCD w % 8. Give each
 // XCD a contiguous run of logical tiles so that tiles sharing ghost rows share
@@ -55,7 +66,7 @@ template <typename T>
 __device__ __forceinline__ T plm_slope(T wm, T w0, T wp) {
   const T dl = w0 - wm, dr = wp - w0;
   const T prod = dl * dr;
-  const T s = (T(2) * prod) / (dl + dr);
+  const T s = (T(2) * prod) * rcp(dl + dr);
   return prod > T(0) ? s : T(0);
 }
 
@@ -102,6 +113,10 @@ struct Gas {
   T gamma, gm1, cq;  // cq = (gamma + 1) / (2 gamma)
 };
 
+// The q factor of the pressure-based speeds is folded into one root:
+// a_K q_K = sqrt(gamma/rho_K * max(p_K, p_K + cq (p* - p_K))), which equals
+// a_K when p* <= p_K. The star state uses one reciprocal r = 1/(S_K - S*):
+// fac = m_K r and p_K/m_K * fac = p_K r, with m_K = rho_K (S_K - u_K).
 template <typename T>
 __device__ __forceinline__ void hllc(const Gas<T>& g, T rl, T ul, T vl, T wl, T ugl, T rr,
                                      T ur, T vr, T wr, T ugr, T f[5]) {
@@ -109,15 +124,15 @@ __device__ __forceinline__ void hllc(const Gas<T>& g, T rl, T ul, T vl, T wl, T 
   const T el = ugl + T(0.5) * rl * ((ul * ul + vl * vl) + wl * wl);
   const T er = ugr + T(0.5) * rr * ((ur * ur + vr * vr) + wr * wr);
   const T il = rcp(rl), ir = rcp(rr);
-  const T al = sqrt(g.gamma * pl * il), ar = sqrt(g.gamma * pr * ir);
+  const T gil = g.gamma * il, gir = g.gamma * ir;
+  const T al = rsqrt_(gil * pl), ar = rsqrt_(gir * pr);
 
   const T ppv = T(0.5) * (pl + pr) - T(0.5) * (ur - ul) * (T(0.5) * (rl + rr)) * (T(0.5) * (al + ar));
   const T ps = fmax(ppv, T(0));
-  const T ql = ps <= pl ? T(1) : sqrt(T(1) + g.cq * (ps * rcp(pl) - T(1)));
-  const T qr = ps <= pr ? T(1) : sqrt(T(1) + g.cq * (ps * rcp(pr) - T(1)));
-  const T sl = ul - al * ql, sr = ur + ar * qr;
+  const T sl = ul - rsqrt_(gil * fmax(pl, pl + g.cq * (ps - pl)));
+  const T sr = ur + rsqrt_(gir * fmax(pr, pr + g.cq * (ps - pr)));
   const T ml = rl * (sl - ul), mr = rr * (sr - ur);
-  const T sst = ((pr - pl) + ml * ul - mr * ur) / (ml - mr);
+  const T sst = ((pr - pl) + ml * ul - mr * ur) * rcp(ml - mr);
 
   const bool c1 = sl >= T(0), c2 = sst >= T(0), c3 = sr > T(0);
   const bool useL = c1 || c2;                 // side K of the selected flux
@@ -130,9 +145,10 @@ __device__ __forceinline__ void hllc(const Gas<T>& g, T rl, T ul, T vl, T wl, T 
   const T mu = rk * uk;
   const T fk0 = mu, fk1 = mu * uk + pk, fk2 = mu * vk, fk3 = mu * wk, fk4 = uk * (ek + pk);
 
-  const T fac = mk / (sk - sst);
+  const T rs = rcp(sk - sst);
+  const T fac = mk * rs;
   const T us0 = fac, us1 = fac * sst, us2 = fac * vk, us3 = fac * wk;
-  const T us4 = fac * (ek * ik + (sst - uk) * (sst + pk / mk));
+  const T us4 = fac * (ek * ik + (sst - uk) * sst) + (sst - uk) * pk * rs;
   f[0] = direct ? fk0 : fk0 + sk * (us0 - rk);
   f[1] = direct ? fk1 : fk1 + sk * (us1 - mu);
   f[2] = direct ? fk2 : fk2 + sk * (us2 - rk * vk);
@@ -157,7 +173,7 @@ __device__ __forceinline__ void c2p(const Floors& fl, const double u[5], double 
   double rho = u[0];
   const bool fr = rho < fl.rho;
   rho = fr ? fl.rho : rho;
-  const double irho = 1.0 / rho;
+  const double irho = rcp(rho);
   const double ke2 = (u[1] * u[1] + u[2] * u[2]) + u[3] * u[3];
   double ug = u[4] - (0.5 * ke2) * irho;
   const bool fu = ug < fl.ug;
@@ -176,10 +192,10 @@ __device__ __forceinline__ double cell_dt(const Floors& fl, double gamma, double
   double w[5];
   int h = 0, b = 0;
   c2p(fl, u, w, h, b);
-  const double cs = sqrt(gamma * (gm1 * w[4]) / w[0]);
-  double m = dx[0] / (fabs(w[1]) + cs);
-  m = fmin(m, dx[1] / (fabs(w[2]) + cs));
-  m = fmin(m, dx[2] / (fabs(w[3]) + cs));
+  const double cs = sqrt(gamma * (gm1 * w[4]) * rcp(w[0]));
+  double m = dx[0] * rcp(fabs(w[1]) + cs);
+  m = fmin(m, dx[1] * rcp(fabs(w[2]) + cs));
+  m = fmin(m, dx[2] * rcp(fabs(w[3]) + cs));
   return m;
 }
 
@@ -281,8 +297,9 @@ __device__ __forceinline__ void zflux(const Gas<T>& g, const T wl[5], const T wr
 // -------------------------------------------------------------- the stage
 // Stage 1: V = U + dt L(U).   Stage 2: U = U/2 + V/2 + dt L(V)/2, then the
 // minimum of dx_d/lambda_d over the new U for the next time step.
-template <int RECON, typename T, int TX, int TY, int STAGE>
-__global__ void __launch_bounds__(TX* TY) k_stage(const StageArgs a) {
+template <int RECON, typename T, int TX, int TY, int WPE, int STAGE>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_stage(const StageArgs a) {
   constexpr int NG = RECON == 0 ? 2 : 3;
   constexpr int NT = TX * TY;
   constexpr int SX = TX + 2 * NG;
@@ -420,10 +437,6 @@ __global__ void __launch_bounds__(TX* TY) k_stage(const StageArgs a) {
     }
 
     for (int k = k0; k < kend; ++k) {
-      // ---- next plane of the owned column (latency overlaps the face work)
-      double un[5];
-      if (own) col_load(k + (RECON == 0 ? 2 : 3), un);
-
       // ---- primitives of plane k into LDS: owned cells from the queue,
       //      ghost cells of the tile from neighbours / boundary conditions
       if (own) {
@@ -521,6 +534,8 @@ __global__ void __launch_bounds__(TX* TY) k_stage(const StageArgs a) {
       // ---- z-face k+1/2 of the owned column (registers only)
       double fz[5];
       if (own) {
+        double un[5];
+        col_load(k + (RECON == 0 ? 2 : 3), un);
         if constexpr (RECON == 0) {
           T w2[5];
           to_prim(un, w2, k + 2);
@@ -704,20 +719,25 @@ __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32
 
 // ------------------------------------------------------ dispatch tables
 // Compiled tile shapes (TX x TY threads); TX*TY must be a multiple of 64.
-#define HY_STAGE_SET(TX, TY)                                                              \
-  {TX, TY,                                                                                \
-   {{{(const void*)&k_stage<0, double, TX, TY, 1>, (const void*)&k_stage<0, double, TX, TY, 2>}, \
-     {(const void*)&k_stage<0, float, TX, TY, 1>, (const void*)&k_stage<0, float, TX, TY, 2>}},   \
-    {{(const void*)&k_stage<1, double, TX, TY, 1>, (const void*)&k_stage<1, double, TX, TY, 2>}, \
-     {(const void*)&k_stage<1, float, TX, TY, 1>, (const void*)&k_stage<1, float, TX, TY, 2>}}}}
+// Compiled tile shapes: TX x TY threads (a multiple of 64) and the occupancy
+// the register allocator targets (waves per SIMD; more waves hide latency
+// better but may force spills).
+#define HY_K(R, T, TX, TY, W, S) (const void*)&k_stage<R, T, TX, TY, W, S>
+#define HY_STAGE_SET(TX, TY, W)                                                       \
+  {TX, TY, W,                                                                         \
+   {{{HY_K(0, double, TX, TY, W, 1), HY_K(0, double, TX, TY, W, 2)},                  \
+     {HY_K(0, float, TX, TY, W, 1), HY_K(0, float, TX, TY, W, 2)}},                   \
+    {{HY_K(1, double, TX, TY, W, 1), HY_K(1, double, TX, TY, W, 2)},                  \
+     {HY_K(1, float, TX, TY, W, 1), HY_K(1, float, TX, TY, W, 2)}}}}
 
 struct StageVariant {
-  int tx, ty;
+  int tx, ty, wpe;
   const void* fn[2][2][2];  // [recon][precision][stage-1]
 };
 
 static const StageVariant kStageVariants[] = {
-    HY_STAGE_SET(64, 8), HY_STAGE_SET(32, 8), HY_STAGE_SET(64, 4), HY_STAGE_SET(16, 16),
+    HY_STAGE_SET(64, 8, 2), HY_STAGE_SET(64, 8, 4), HY_STAGE_SET(32, 8, 2), HY_STAGE_SET(32, 8, 3),
+    HY_STAGE_SET(32, 8, 4), HY_STAGE_SET(16, 16, 4), HY_STAGE_SET(64, 4, 3), HY_STAGE_SET(32, 16, 2),
 };
 
 int num_stage_variants() { return (int)(sizeof(kStageVariants) / sizeof(kStageVariants[0])); }
