@@ -56,6 +56,13 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0)
+    ap.add_argument("--launch", default="auto",
+                    help="tile variant and z-chunk as V,KC (FP64 and mixed), or 'auto' to autotune")
+    ap.add_argument("--batch", action="store_true",
+                    help="also run the 48-problem Sedov batch (mixed, 50 steps)")
+    ap.add_argument("--serve", type=int, default=0, metavar="COUNT",
+                    help="also serve COUNT requests of the seeded Poisson stream")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -85,6 +92,11 @@ def main():
 
     def run(precision):
         g = hy.Problem(pb.with_(precision=precision)).set_state()
+        if args.launch == "auto":
+            g.autotune()
+        else:
+            v, kc = (int(x) for x in args.launch.split(","))
+            g.set_launch(v, kc)
         g.advance(args.warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -119,6 +131,7 @@ def main():
                         f"{args.block}^3, PLM+HLLC, SSP-RK2, CFL 0.3, rho=1 P=1, rms Mach 0.5, seed 1",
             "cells": cells,
             "tile_variant": list(hy.variants()[r64["launch"][0]]) + [r64["launch"][1]],
+            "launch": list(r64["launch"]),
         },
     }
 
@@ -140,7 +153,7 @@ def main():
         "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
         "traffic": traffic,
-        "kernel": f"k_stage stage {dom} (FP64, PLM)",
+        "kernel": "k_stage<0, double, {}, {}, {}, {}>".format(*hy.variants_full()[r64["launch"][0]], dom),
         "avg_launch_ms": avg * 1e3,
         "other_stage_avg_launch_ms": (a1 if dom == 2 else a2) * 1e3,
         "bytes_per_cell": BYTES_STAGE[dom],
@@ -155,6 +168,7 @@ def main():
             "ms_per_step": 1e3 * rmx["sec"] / args.steps,
             "stage1_ms": rmx["ms1"] / args.steps,
             "stage2_ms": rmx["ms2"] / args.steps,
+            "tile_variant": list(hy.variants()[rmx["launch"][0]]) + [rmx["launch"][1]],
             "rel_l1_vs_fp64_gpu": rel,
             "dtype": "f32 reconstruct/Riemann, f64 state/divergence/dt",
         }
@@ -177,7 +191,93 @@ def main():
         }
         assert r["status"] == 0
 
+    if args.batch:
+        out["batch"] = run_batch_workload(hy, P, torch)
+    if args.serve:
+        out["serving"] = run_serving_workload(hy, P, args.serve, args.serve_budget_gb)
+
     print(json.dumps(out), flush=True)
+
+
+def run_batch_workload(hy, P, torch, count=48, seed=3):
+    """48 independent Sedov problems (sizes drawn by seed from 32..128^3),
+    outflow, PLM + HLLC, RK2, 50 steps each, mixed precision: aggregate
+    cell-updates/s with one launch per RK stage for all problems, against the
+    same problems advanced one at a time."""
+    pbs, steps = P.workload_sedov_batch(count=count, seed=seed)
+    cells = sum(p.cells for p in pbs)
+    log(f"batch: {count} Sedov problems, {cells} cells, {steps} steps")
+    gs = [hy.Problem(p) for p in pbs]
+    tuned = {}
+    for g, p in zip(gs, pbs):       # autotune once per size class
+        g.set_state()
+        key = p.n
+        if key not in tuned:
+            tuned[key] = g.autotune()
+        else:
+            g.set_launch(*tuned[key][:2])
+    torch.cuda.synchronize()
+    # one at a time
+    t0 = time.perf_counter()
+    for g in gs:
+        g.advance(steps)
+        torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    for g in gs:
+        g.set_state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hy.batch_advance(gs, steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    floors = sum(g.query()["floor_hits"] for g in gs)
+    for g in gs:
+        g.close()
+    return {
+        "value": cells * steps / t_batch,
+        "unit": "cell-updates/s",
+        "one_by_one": cells * steps / t_one,
+        "speedup": t_one / t_batch,
+        "problems": count,
+        "cells": cells,
+        "steps": steps,
+        "dtype": "mixed",
+        "size_classes": {f"{k[0]}^3": list(v[:2]) for k, v in tuned.items()},
+        "floor_hits": floors,
+    }
+
+
+def run_serving_workload(hy, P, count, budget_gb, seed=4, epoch=10):
+    """Poisson stream of Sod / KH / Sedov requests (32^3..256^3, 10..200
+    steps, FP64 or mixed), admitted by an HBM budget: continuous batching
+    against one request at a time. The arrival rate is 0.8 / (mean service
+    time of the one-at-a-time path on the first requests)."""
+    from paper_2409_16053_amd import serve
+    calib = min(count, 24)
+    probe = serve.make_stream(seed, calib, rate=1e9)
+    t0 = time.perf_counter()
+    serve.run_fifo(probe)
+    mean_service = (time.perf_counter() - t0) / calib
+    rate = 0.8 / mean_service
+    log(f"serving: mean one-at-a-time service {mean_service * 1e3:.1f} ms -> rate {rate:.1f}/s")
+    budget = int(budget_gb * 2 ** 30)
+    fifo = serve.run_fifo(serve.make_stream(seed, count, rate))
+    sf = serve.summarize(fifo)
+    srv = serve.Server(budget_bytes=budget, epoch_steps=epoch)
+    cont = srv.run(serve.make_stream(seed, count, rate))
+    sc = serve.summarize(cont)
+    same = all(np.array_equal(a.result, b.result) for a, b in zip(cont, fifo)
+               if a.result is not None and b.result is not None)
+    return {
+        "requests": count,
+        "rate_per_s": rate,
+        "budget_gb": budget_gb,
+        "epoch_steps": epoch,
+        "continuous": sc,
+        "fifo": sf,
+        "peak_resident_gb": srv.peak_bytes / 2 ** 30,
+        "results_equal_alone": bool(same),
+    }
 
 
 if __name__ == "__main__":

@@ -134,11 +134,12 @@ const char* hy_last_error(void);
 
 /* ---------------- launch shapes and tuning -------------------------------
  * The stage kernel works on x-y tiles of a MeshBlock, marching along z over
- * chunks of kc planes. The compiled tile shapes (tx, ty) are listed by
- * hy_num_variants/hy_variant_info; kc is any value >= 1. Results do not
- * depend on the shape. */
+ * chunks of kc planes. The compiled variants -- tile shape (tx, ty) and the
+ * occupancy (waves per SIMD) the register allocator targets -- are listed by
+ * hy_num_variants/hy_variant_info (any out pointer may be NULL); kc is any
+ * value >= 1. Results do not depend on the variant or on kc. */
 int32_t hy_num_variants(void);
-hy_status hy_variant_info(int32_t variant, int32_t* tx, int32_t* ty);
+hy_status hy_variant_info(int32_t variant, int32_t* tx, int32_t* ty, int32_t* waves_per_simd);
 hy_status hy_set_launch(hy_problem* p, int32_t variant, int32_t kc);
 hy_status hy_get_launch(const hy_problem* p, int32_t* variant, int32_t* kc);
 

@@ -109,13 +109,22 @@ void default_launch(const hy_problem* p, int* variant, int* kc) {
       return;
     }
   }
-  // x tile as wide as the block allows (full 64-lane rows), else narrower
-  int v = 3;  // 16 x 16
-  for (int i = 0; i < num_stage_variants(); ++i) {
+  // Preferred shapes from measurement on the 256^3 workload: FP64 does best
+  // with 32x8 tiles at 3 waves per SIMD, mixed with 16x16 at 4; fall back to
+  // the first variant whose width divides the block.
+  const int pref[2][2] = {{3, 5}, {5, 4}};
+  int v = -1;
+  for (int c : pref[p->cfg.precision == HY_MIXED ? 1 : 0]) {
+    int tx, ty;
+    stage_variant_shape(c, &tx, &ty);
+    if (c < num_stage_variants() && bx % tx == 0) { v = c; break; }
+  }
+  for (int i = 0; v < 0 && i < num_stage_variants(); ++i) {
     int tx, ty;
     stage_variant_shape(i, &tx, &ty);
-    if (bx % tx == 0) { v = i; break; }
+    if (bx % tx == 0) v = i;
   }
+  if (v < 0) v = 0;
   int tx, ty;
   stage_variant_shape(v, &tx, &ty);
   const int64_t cols = (int64_t)((bx + tx - 1) / tx) * ((p->cfg.block[1] + ty - 1) / ty);
@@ -406,12 +415,13 @@ const char* hy_last_error(void) { return g_err.c_str(); }
 
 int32_t hy_num_variants(void) { return num_stage_variants(); }
 
-hy_status hy_variant_info(int32_t v, int32_t* tx, int32_t* ty) {
-  if (v < 0 || v >= num_stage_variants() || !tx || !ty) return fail(HY_ERR_ARG, "bad variant");
+hy_status hy_variant_info(int32_t v, int32_t* tx, int32_t* ty, int32_t* waves) {
+  if (v < 0 || v >= num_stage_variants()) return fail(HY_ERR_ARG, "bad variant");
   int a, b;
   stage_variant_shape(v, &a, &b);
-  *tx = a;
-  *ty = b;
+  if (tx) *tx = a;
+  if (ty) *ty = b;
+  if (waves) *waves = stage_variant_waves(v);
   return HY_OK;
 }
 

@@ -294,6 +294,47 @@ __device__ __forceinline__ void zflux(const Gas<T>& g, const T wl[5], const T wr
   f[4] = (double)h[4];
 }
 
+// ------------------------------------------------------------ one face
+// Flux through the face between LDS cells (base - STR) and base along
+// direction DIR (0 = x, 1 = y), in conserved-variable order. PLM reads two
+// cells on each side, PPM4 three.
+template <int RECON, int DIR, typename T, int STR, int PLANE>
+__device__ __forceinline__ void face_flux(const Gas<T>& gas, const T* __restrict__ sW, int base,
+                                          T out[5]) {
+  T wl[5], wr[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const T* s = sW + v * PLANE + base;
+    if constexpr (RECON == 0) {
+      const T c0 = s[-2 * STR], c1 = s[-STR], c2 = s[0], c3 = s[STR];
+      wl[v] = c1 + T(0.5) * plm_slope(c0, c1, c2);
+      wr[v] = c2 - T(0.5) * plm_slope(c1, c2, c3);
+    } else {
+      const T c0 = s[-3 * STR], c1 = s[-2 * STR], c2 = s[-STR];
+      const T c3 = s[0], c4 = s[STR], c5 = s[2 * STR];
+      const T d1 = ppm_dm(c0, c1, c2), d2 = ppm_dm(c1, c2, c3);
+      const T d3 = ppm_dm(c2, c3, c4), d4 = ppm_dm(c3, c4, c5);
+      const T am = ppm_iface(c1, c2, d1, d2);
+      const T a0 = ppm_iface(c2, c3, d2, d3);
+      const T ap = ppm_iface(c3, c4, d3, d4);
+      T l1 = am, r1 = a0;
+      ppm_mono(c2, l1, r1);
+      T l2 = a0, r2 = ap;
+      ppm_mono(c3, l2, r2);
+      wl[v] = r1;
+      wr[v] = l2;
+    }
+  }
+  T f[5];
+  if constexpr (DIR == 0) {  // (n, t1, t2) = (vx, vy, vz)
+    hllc(gas, wl[0], wl[1], wl[2], wl[3], wl[4], wr[0], wr[1], wr[2], wr[3], wr[4], f);
+    out[0] = f[0]; out[1] = f[1]; out[2] = f[2]; out[3] = f[3]; out[4] = f[4];
+  } else {                   // (n, t1, t2) = (vy, vz, vx)
+    hllc(gas, wl[0], wl[2], wl[3], wl[1], wl[4], wr[0], wr[2], wr[3], wr[1], wr[4], f);
+    out[0] = f[0]; out[2] = f[1]; out[3] = f[2]; out[1] = f[3]; out[4] = f[4];
+  }
+}
+
 // -------------------------------------------------------------- the stage
 // Stage 1: V = U + dt L(U).   Stage 2: U = U/2 + V/2 + dt L(V)/2, then the
 // minimum of dx_d/lambda_d over the new U for the next time step.
@@ -308,6 +349,8 @@ k_stage(const StageArgs a) {
   constexpr int NXF = (TX + 1) * TY;
   constexpr int NYF = TX * (TY + 1);
   constexpr int NF = NXF + NYF;
+  constexpr int NXFP = (NXF + kWave - 1) / kWave * kWave;
+  constexpr int NFP = NXFP + NYF;
   constexpr int NHX = 2 * NG * TY;
   constexpr int NH = NHX + 2 * NG * TX;
   constexpr int NWAVE = NT / kWave;
@@ -473,61 +516,29 @@ k_stage(const StageArgs a) {
       }
       __syncthreads();
 
-      // ---- x- and y-faces of plane k, spread over all threads
-      for (int w = tid; w < NF; w += NT) {
-        int fi, fj, dir, base, stride;
-        bool ok;
-        if (w < NXF) {
-          fj = w / (TX + 1);
-          fi = w - fj * (TX + 1);
-          dir = 0;
-          ok = fi <= nxv && fj < nyv;
-          base = (fj + NG) * SX + (fi + NG);
-          stride = 1;
-        } else {
-          const int ww = w - NXF;
-          fj = ww / TX;
-          fi = ww - fj * TX;
-          dir = 1;
-          ok = fi < nxv && fj <= nyv;
-          base = (fj + NG) * SX + (fi + NG);
-          stride = SX;
-        }
-        if (ok) {
-          T wl[5], wr[5];
+      // ---- x- and y-faces of plane k, spread over all threads. The x-face
+      //      items are padded to whole wavefronts so that every wavefront
+      //      runs a single direction.
+      for (int w = tid; w < NFP; w += NT) {
+        if (w < NXFP) {
+          const int fj = w / (TX + 1);
+          const int fi = w - fj * (TX + 1);
+          if (w < NXF && fi <= nxv && fj < nyv) {
+            T f[5];
+            face_flux<RECON, 0, T, 1, PLANE>(gas, sW, (fj + NG) * SX + (fi + NG), f);
 #pragma unroll
-          for (int v = 0; v < 5; ++v) {
-            const T* s = sW + v * PLANE + base;
-            if constexpr (RECON == 0) {
-              const T c0 = s[-2 * stride], c1 = s[-stride], c2 = s[0], c3 = s[stride];
-              wl[v] = c1 + T(0.5) * plm_slope(c0, c1, c2);
-              wr[v] = c2 - T(0.5) * plm_slope(c1, c2, c3);
-            } else {
-              const T c0 = s[-3 * stride], c1 = s[-2 * stride], c2 = s[-stride];
-              const T c3 = s[0], c4 = s[stride], c5 = s[2 * stride];
-              const T d1 = ppm_dm(c0, c1, c2), d2 = ppm_dm(c1, c2, c3);
-              const T d3 = ppm_dm(c2, c3, c4), d4 = ppm_dm(c3, c4, c5);
-              const T am = ppm_iface(c1, c2, d1, d2);
-              const T a0 = ppm_iface(c2, c3, d2, d3);
-              const T ap = ppm_iface(c3, c4, d3, d4);
-              T l1 = am, r1 = a0;
-              ppm_mono(c2, l1, r1);
-              T l2 = a0, r2 = ap;
-              ppm_mono(c3, l2, r2);
-              wl[v] = r1;
-              wr[v] = l2;
-            }
+            for (int v = 0; v < 5; ++v) sF[v * NF + w] = f[v];
           }
-          // rotate: x-face (n,t1,t2) = (vx,vy,vz); y-face = (vy,vz,vx)
-          const T nl = dir ? wl[2] : wl[1], al = dir ? wl[3] : wl[2], bl = dir ? wl[1] : wl[3];
-          const T nr = dir ? wr[2] : wr[1], ar = dir ? wr[3] : wr[2], br = dir ? wr[1] : wr[3];
-          T f[5];
-          hllc(gas, wl[0], nl, al, bl, wl[4], wr[0], nr, ar, br, wr[4], f);
-          sF[0 * NF + w] = f[0];
-          sF[1 * NF + w] = dir ? f[3] : f[1];
-          sF[2 * NF + w] = dir ? f[1] : f[2];
-          sF[3 * NF + w] = dir ? f[2] : f[3];
-          sF[4 * NF + w] = f[4];
+        } else {
+          const int ww = w - NXFP;
+          const int fj = ww / TX;
+          const int fi = ww - fj * TX;
+          if (fi < nxv && fj <= nyv) {
+            T f[5];
+            face_flux<RECON, 1, T, SX, PLANE>(gas, sW, (fj + NG) * SX + (fi + NG), f);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sF[v * NF + NXF + ww] = f[v];
+          }
         }
       }
 
@@ -746,6 +757,8 @@ void stage_variant_shape(int v, int* tx, int* ty) {
   *tx = kStageVariants[v].tx;
   *ty = kStageVariants[v].ty;
 }
+
+int stage_variant_waves(int v) { return kStageVariants[v].wpe; }
 
 const void* stage_kernel(int v, int recon, int prec, int stage) {
   return kStageVariants[v].fn[recon][prec][stage - 1];

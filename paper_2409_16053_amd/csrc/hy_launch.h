@@ -5,6 +5,7 @@
 namespace hy {
 int num_stage_variants();
 void stage_variant_shape(int v, int* tx, int* ty);
+int stage_variant_waves(int v);
 const void* stage_kernel(int v, int recon, int prec, int stage);
 hipError_t launch_stage(int v, int recon, int prec, int stage, const StageArgs& a, int grid,
                         hipStream_t s);

@@ -58,7 +58,7 @@ SIGNATURES = {
     "hy_destroy": ([_vp], _c.c_int),
     "hy_last_error": ([], _c.c_char_p),
     "hy_num_variants": ([], _c.c_int32),
-    "hy_variant_info": ([_c.c_int32, _i32p, _i32p], _c.c_int),
+    "hy_variant_info": ([_c.c_int32, _i32p, _i32p, _i32p], _c.c_int),
     "hy_set_launch": ([_vp, _c.c_int32, _c.c_int32], _c.c_int),
     "hy_get_launch": ([_vp, _i32p, _i32p], _c.c_int),
     "hy_autotune": ([_vp, _vp, _i32p, _i32p, _dp], _c.c_int),
@@ -141,13 +141,19 @@ def workspace_bytes(pb) -> int:
     return int(n)
 
 
-def variants():
+def variants_full():
+    """Compiled stage-kernel variants as (tx, ty, waves per SIMD)."""
     out = []
     for v in range(lib().hy_num_variants()):
-        tx, ty = _c.c_int32(), _c.c_int32()
-        _check(lib().hy_variant_info(v, _c.byref(tx), _c.byref(ty)))
-        out.append((tx.value, ty.value))
+        tx, ty, w = _c.c_int32(), _c.c_int32(), _c.c_int32()
+        _check(lib().hy_variant_info(v, _c.byref(tx), _c.byref(ty), _c.byref(w)))
+        out.append((tx.value, ty.value, w.value))
     return out
+
+
+def variants():
+    """Tile shapes (tx, ty) of the compiled stage-kernel variants."""
+    return [(a, b) for a, b, _ in variants_full()]
 
 
 class Problem:

@@ -277,9 +277,14 @@ def kelvin_helmholtz(N=512, seed=2, n=None, gamma=5.0 / 3.0, noise=1e-2, **kw):
     shape = (nz, ny, nx)
     rho = np.broadcast_to(rho_y[None, :, None], shape)
     vx = np.broadcast_to(vx_y[None, :, None], shape)
-    idx = np.arange(nx * ny * nz, dtype=np.uint64).reshape(shape)
-    r = uniform01(seed, idx)
-    vy = np.where(band[None, :, None], noise * (2.0 * r - 1.0), 0.0)
+    vy = np.zeros(shape)
+    rows = np.nonzero(band)[0]
+    if rows.size:  # hash only the band rows; the cell index is the global one
+        k = np.arange(nz, dtype=np.uint64)[:, None, None]
+        j = rows.astype(np.uint64)[None, :, None]
+        i = np.arange(nx, dtype=np.uint64)[None, None, :]
+        idx = i + np.uint64(nx) * (j + np.uint64(ny) * k)
+        vy[:, rows, :] = noise * (2.0 * uniform01(seed, idx) - 1.0)
     U = conserved(rho, vx, vy, 0.0, np.full(shape, 2.5), gamma)
     bcs = ((PERIODIC, PERIODIC),) * 3
     return Problem(n=tuple(n), lo=lo, hi=hi, bc=bcs, U=U, gamma=gamma,
@@ -392,22 +397,40 @@ SERVE_SIZES = (32, 48, 64, 96, 128, 192, 256)
 SERVE_STEPS = (10, 20, 50, 100, 200)
 
 
-def serving_request(seed: int, index: int):
+def serving_request(seed: int, index: int, max_n: int | None = None, generate: bool = True):
     """Request ``index`` of the seeded serving stream: (problem, steps).
 
-    Type, size, step count and precision are each uniform over their grids;
-    the draws for one request depend only on (seed, index).
+    Type, size, step count and precision are each uniform over their grids
+    (``max_n`` drops larger sizes from the size grid); the draws for one
+    request depend only on (seed, index). With ``generate=False`` the problem
+    carries no state yet (``U is None``): ``generate_state`` builds it.
     """
     r = uniform01(seed, np.arange(4, dtype=np.uint64) + np.uint64(4 * index))
     typ = SERVE_TYPES[int(r[0] * len(SERVE_TYPES))]
-    N = SERVE_SIZES[int(r[1] * len(SERVE_SIZES))]
+    sizes = SERVE_SIZES if max_n is None else tuple(x for x in SERVE_SIZES if x <= max_n)
+    N = sizes[int(r[1] * len(sizes))]
     steps = SERVE_STEPS[int(r[2] * len(SERVE_STEPS))]
     prec = FP64 if r[3] < 0.5 else MIXED
     sub = seed * 1_000_003 + index
-    if typ == "sod":
-        pb = sod(N=N, seed=sub)
-    elif typ == "kh":
-        pb = kelvin_helmholtz(N=N, seed=sub)
+    if typ == "kh":
+        lo, hi, bc = (-0.5,) * 3, (0.5,) * 3, ((PERIODIC, PERIODIC),) * 3
     else:
-        pb = sedov(N=N, seed=sub)
-    return pb.with_(block=_default_block(pb.n), recon=PLM, precision=prec), steps
+        lo, hi, bc = (0.0,) * 3, (1.0,) * 3, ((OUTFLOW, OUTFLOW),) * 3
+    pb = Problem(n=(N, N, N), lo=lo, hi=hi, bc=bc, U=None, recon=PLM, precision=prec,
+                 block=_default_block((N, N, N)), name=typ, meta=dict(kind=typ, N=N, sub=sub))
+    if generate:
+        pb = pb.with_(U=generate_state(pb))
+    return pb, steps
+
+
+def generate_state(pb) -> np.ndarray:
+    """Conserved state of a serving-stream problem built from its metadata."""
+    kind, N, sub = pb.meta["kind"], pb.meta["N"], pb.meta["sub"]
+    if kind == "sod":
+        full = sod(N=N, seed=sub)
+    elif kind == "kh":
+        full = kelvin_helmholtz(N=N, seed=sub)
+    else:
+        full = sedov(N=N, seed=sub)
+    assert full.n == tuple(pb.n) and full.bc == pb.bc and full.lo == pb.lo
+    return full.U
