@@ -92,17 +92,29 @@ size_t hy_workspace_bytes(const hy_config* cfg);
  * undefined until hy_set_state. */
 hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_problem** out);
 
-/* Load the conserved state. U is the GLOBAL interior state as
- * double[5][nz][ny][nx], x fastest, variables rho, Mx, My, Mz, E; a device
- * pointer if on_device != 0, else a host pointer. The library scatters it into
- * its MeshBlocks and computes the first time step from it (Eq. 3). Async for
- * device input; host input is copied before return. Resets neither t nor the
- * step count. */
-hy_status hy_set_state(hy_problem* p, const double* U, int on_device, void* hip_stream);
+/* Where a state buffer lives (the `where` argument of hy_set_state and
+ * hy_get_state). */
+enum {
+  HY_HOST = 0,        /* pageable host memory; the call waits for the copy     */
+  HY_DEVICE = 1,      /* device memory; the call only enqueues work            */
+  HY_HOST_PINNED = 2  /* page-locked host memory; the call only enqueues work
+                         and the caller keeps the buffer untouched until the
+                         stream has passed this point                         */
+};
 
-/* Store the conserved state into U (same layout as hy_set_state). Waits for
- * the stream, then reports HY_ERR_STATE if the device flagged a bad state. */
-hy_status hy_get_state(hy_problem* p, double* U, int on_device, void* hip_stream);
+/* Load the conserved state. U is the GLOBAL interior state as
+ * double[5][nz][ny][nx], x fastest, variables rho, Mx, My, Mz, E, located as
+ * `where` says. The library scatters it into its MeshBlocks (host data is
+ * staged through the problem's second state register) and computes the first
+ * time step from it (Eq. 3). Clears the bad-state flag. Resets neither t nor
+ * the step count. */
+hy_status hy_set_state(hy_problem* p, const double* U, int where, void* hip_stream);
+
+/* Store the conserved state into U (same layout as hy_set_state). For
+ * HY_HOST and HY_DEVICE it waits for the stream and then reports HY_ERR_STATE
+ * if the device flagged a bad state; for HY_HOST_PINNED it only enqueues the
+ * copy (check the flag later with hy_query). */
+hy_status hy_get_state(hy_problem* p, double* U, int where, void* hip_stream);
 
 /* Advance nsteps >= 0 full RK2 steps (async). Each step uses the time step
  * computed on the device at the end of the previous one; the host never reads
@@ -144,12 +156,15 @@ hy_status hy_set_launch(hy_problem* p, int32_t variant, int32_t kc);
 hy_status hy_get_launch(const hy_problem* p, int32_t* variant, int32_t* kc);
 
 /* Time every compiled tile shape and a few z-chunk lengths on this problem's
- * own state (stage-1 launches only, which leave the state unchanged), keep the
- * fastest for this problem and cache it for its (block size, recon,
- * precision) class. Synchronous. Returns the chosen shape in *variant/*kc
- * (either may be NULL) and its time per stage in *us_per_stage. */
-hy_status hy_autotune(hy_problem* p, void* hip_stream, int32_t* variant, int32_t* kc,
-                      double* us_per_stage);
+ * own state, keep the fastest for this problem and cache it for its (block
+ * size, recon, precision) class. With full_steps == 0 only stage-1 launches
+ * are timed, which leave the state unchanged; with full_steps > 0 each
+ * candidate runs that many complete RK2 steps after one warm-up step, which
+ * ADVANCES the state (tune a scratch copy). Synchronous. Returns the chosen
+ * shape in *variant/*kc (either may be NULL) and its time per stage in
+ * *us_per_stage. */
+hy_status hy_autotune(hy_problem* p, void* hip_stream, int32_t full_steps, int32_t* variant,
+                      int32_t* kc, double* us_per_stage);
 
 /* ---------------- measurement helpers ------------------------------------- */
 /* Copy `bytes` (a multiple of 16) from device src to device dst with a plain

@@ -334,12 +334,14 @@ hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_prob
   return HY_OK;
 }
 
-hy_status hy_set_state(hy_problem* p, const double* U, int on_device, void* stream) {
+hy_status hy_set_state(hy_problem* p, const double* U, int where, void* stream) {
   if (!p || !U) return fail(HY_ERR_ARG, "NULL argument");
+  if (where != HY_HOST && where != HY_DEVICE && where != HY_HOST_PINNED)
+    return fail(HY_ERR_ARG, "bad buffer location");
   hipStream_t s = (hipStream_t)stream;
   const double* src = U;
   const size_t bytes = (size_t)p->ncell * 5 * sizeof(double);
-  if (!on_device) {
+  if (where != HY_DEVICE) {
     HY_HIP(hipMemcpyAsync(p->hp.V, U, bytes, hipMemcpyHostToDevice, s));
     src = p->hp.V;
   }
@@ -347,22 +349,25 @@ hy_status hy_set_state(hy_problem* p, const double* U, int on_device, void* stre
   const int slot = (int)(p->steps & 1);
   HY_HIP(launch_reset(p->dp, slot, 1, s));
   HY_HIP(launch_dt(p->dp, p->ncell, slot, 1, s));
-  if (!on_device) HY_HIP(hipStreamSynchronize(s));
+  if (where == HY_HOST) HY_HIP(hipStreamSynchronize(s));
   p->last = s;
   return HY_OK;
 }
 
-hy_status hy_get_state(hy_problem* p, double* U, int on_device, void* stream) {
+hy_status hy_get_state(hy_problem* p, double* U, int where, void* stream) {
   if (!p || !U) return fail(HY_ERR_ARG, "NULL argument");
+  if (where != HY_HOST && where != HY_DEVICE && where != HY_HOST_PINNED)
+    return fail(HY_ERR_ARG, "bad buffer location");
   hipStream_t s = (hipStream_t)stream;
   const size_t bytes = (size_t)p->ncell * 5 * sizeof(double);
-  if (on_device) {
+  if (where == HY_DEVICE) {
     HY_HIP(launch_scatter(p->dp, p->hp.U, U, p->ncell * 5, 0, s));
   } else {
     HY_HIP(launch_scatter(p->dp, p->hp.U, p->hp.V, p->ncell * 5, 0, s));
     HY_HIP(hipMemcpyAsync(U, p->hp.V, bytes, hipMemcpyDeviceToHost, s));
   }
   p->last = s;
+  if (where == HY_HOST_PINNED) return HY_OK;
   DevCounters c;
   hy_status st = read_counters(p, &c);
   if (st != HY_OK) return st;
@@ -440,8 +445,9 @@ hy_status hy_get_launch(const hy_problem* p, int32_t* variant, int32_t* kc) {
   return HY_OK;
 }
 
-hy_status hy_autotune(hy_problem* p, void* stream, int32_t* variant, int32_t* kc, double* us) {
-  if (!p) return fail(HY_ERR_ARG, "NULL problem");
+hy_status hy_autotune(hy_problem* p, void* stream, int32_t full_steps, int32_t* variant,
+                      int32_t* kc, double* us) {
+  if (!p || full_steps < 0) return fail(HY_ERR_ARG, "bad argument");
   hipStream_t s = (hipStream_t)stream;
   const int bz = p->cfg.block[2];
   std::vector<int> kcs;
@@ -463,10 +469,20 @@ hy_status hy_autotune(hy_problem* p, void* stream, int32_t* variant, int32_t* kc
       p->variant = v;
       p->kc = k;
       Plan pl{v, p->cfg.recon, p->cfg.precision, {0}};
-      st = launch_group(ps, act, pl, 1, step_of, 0, s);  // warm-up
-      if (st != HY_OK) break;
-      if (hipEventRecord(e0, s) != hipSuccess) { st = fail(HY_ERR_HIP, "event record"); break; }
-      for (int r = 0; r < 3 && st == HY_OK; ++r) st = launch_group(ps, act, pl, 1, step_of, 0, s);
+      const int reps = full_steps > 0 ? full_steps : 3;
+      if (full_steps > 0) {
+        int32_t one = 1;
+        st = run_batch(ps, &one, 1, s, nullptr, 0);  // warm-up step
+        if (st != HY_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(HY_ERR_HIP, "event record"); break; }
+        int32_t n = full_steps;
+        st = run_batch(ps, &n, 1, s, nullptr, 0);
+      } else {
+        st = launch_group(ps, act, pl, 1, step_of, 0, s);  // warm-up
+        if (st != HY_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(HY_ERR_HIP, "event record"); break; }
+        for (int r = 0; r < reps && st == HY_OK; ++r) st = launch_group(ps, act, pl, 1, step_of, 0, s);
+      }
       if (st != HY_OK) break;
       if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
         st = fail(HY_ERR_HIP, "event sync");
@@ -494,7 +510,7 @@ hy_status hy_autotune(hy_problem* p, void* stream, int32_t* variant, int32_t* kc
   }
   if (variant) *variant = bv;
   if (kc) *kc = bk;
-  if (us) *us = best * 1000.0 / 3.0;
+  if (us) *us = best * 1000.0 / (full_steps > 0 ? 2.0 * full_steps : 3.0);
   return HY_OK;
 }
 

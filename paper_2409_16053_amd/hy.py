@@ -19,6 +19,7 @@ HY_OK, HY_ERR_ARG, HY_ERR_NOMEM, HY_ERR_HIP, HY_ERR_STATE, HY_ERR_BUDGET = range
 PERIODIC, OUTFLOW = 0, 1
 PLM, PPM4 = 0, 1
 FP64, MIXED = 0, 1
+HOST, DEVICE, HOST_PINNED = 0, 1, 2
 
 # (name, argtypes, restype) of every entry point declared in include/hy.h
 _c = ctypes
@@ -61,7 +62,7 @@ SIGNATURES = {
     "hy_variant_info": ([_c.c_int32, _i32p, _i32p, _i32p], _c.c_int),
     "hy_set_launch": ([_vp, _c.c_int32, _c.c_int32], _c.c_int),
     "hy_get_launch": ([_vp, _i32p, _i32p], _c.c_int),
-    "hy_autotune": ([_vp, _vp, _i32p, _i32p, _dp], _c.c_int),
+    "hy_autotune": ([_vp, _vp, _c.c_int32, _i32p, _i32p, _dp], _c.c_int),
     "hy_copy_probe": ([_vp, _vp, _c.c_size_t, _vp], _c.c_int),
     "hy_advance_timed": ([_vp, _c.c_int32, _vp, _dp, _dp], _c.c_int),
 }
@@ -179,33 +180,48 @@ class Problem:
 
     # -- state ---------------------------------------------------------
     def set_state(self, U=None, stream=None):
+        """Load a state from a numpy array (pageable host) or a CUDA tensor."""
         torch = _torch()
         U = self.pb.U if U is None else U
         if isinstance(U, torch.Tensor) and U.is_cuda:
             t = U.to(torch.float64).contiguous()
             assert tuple(t.shape) == self.shape
-            _check(lib().hy_set_state(self.h, _vp(t.data_ptr()), 1, _stream(stream)))
+            _check(lib().hy_set_state(self.h, _vp(t.data_ptr()), DEVICE, _stream(stream)))
             self._keep = t
         else:
             a = np.ascontiguousarray(U, dtype=np.float64)
             assert a.shape == self.shape
-            _check(lib().hy_set_state(self.h, _vp(a.ctypes.data), 0, _stream(stream)))
+            _check(lib().hy_set_state(self.h, _vp(a.ctypes.data), HOST, _stream(stream)))
+        return self
+
+    def set_state_pinned(self, t, stream=None):
+        """Enqueue a load from a page-locked float64 CPU tensor; the caller keeps
+        ``t`` alive and unchanged until the stream has passed this point."""
+        assert t.is_pinned() and t.dtype == _torch().float64 and tuple(t.shape) == self.shape
+        _check(lib().hy_set_state(self.h, _vp(t.data_ptr()), HOST_PINNED, _stream(stream)))
         return self
 
     def get_state(self, device=False, stream=None):
         torch = _torch()
         if device:
             out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
-            _check(lib().hy_get_state(self.h, _vp(out.data_ptr()), 1, _stream(stream)))
+            _check(lib().hy_get_state(self.h, _vp(out.data_ptr()), DEVICE, _stream(stream)))
             return out
         out = np.empty(self.shape, dtype=np.float64)
-        _check(lib().hy_get_state(self.h, _vp(out.ctypes.data), 0, _stream(stream)))
+        _check(lib().hy_get_state(self.h, _vp(out.ctypes.data), HOST, _stream(stream)))
+        return out
+
+    def get_state_pinned(self, out, stream=None):
+        """Enqueue a store into a page-locked float64 CPU tensor (check the
+        bad-state flag later with ``query``)."""
+        assert out.is_pinned() and out.dtype == _torch().float64 and tuple(out.shape) == self.shape
+        _check(lib().hy_get_state(self.h, _vp(out.data_ptr()), HOST_PINNED, _stream(stream)))
         return out
 
     def get_state_status(self, stream=None):
         """(status, U) without raising on a device-flagged bad state."""
         out = np.empty(self.shape, dtype=np.float64)
-        st = lib().hy_get_state(self.h, _vp(out.ctypes.data), 0, _stream(stream))
+        st = lib().hy_get_state(self.h, _vp(out.ctypes.data), HOST, _stream(stream))
         return st, out
 
     # -- time stepping ---------------------------------------------------
@@ -238,10 +254,23 @@ class Problem:
         _check(lib().hy_get_launch(self.h, _c.byref(v), _c.byref(k)))
         return v.value, k.value
 
-    def autotune(self, stream=None):
+    def autotune(self, full_steps=0, stream=None):
+        """Pick the fastest compiled variant and z-chunk (see hy_autotune).
+        full_steps > 0 times whole RK2 steps and advances the state."""
         v, k, us = _c.c_int32(), _c.c_int32(), _c.c_double()
-        _check(lib().hy_autotune(self.h, _stream(stream), _c.byref(v), _c.byref(k), _c.byref(us)))
+        _check(lib().hy_autotune(self.h, _stream(stream), int(full_steps), _c.byref(v), _c.byref(k),
+                                 _c.byref(us)))
         return v.value, k.value, us.value
+
+    def autotune_steps(self, full_steps=2):
+        """Tune on whole RK2 steps using a scratch copy of this problem, then
+        apply the choice here (this problem's state is left unchanged)."""
+        scratch = Problem(self.pb, device=self.device)
+        scratch.set_state(self.get_state(device=True))
+        res = scratch.autotune(full_steps=full_steps)
+        scratch.close()
+        self.set_launch(res[0], res[1])
+        return res
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
