@@ -191,12 +191,39 @@ def main():
         }
         assert r["status"] == 0
 
+    out["small_problem"] = run_small_workload(hy, P, torch)
     if args.batch:
         out["batch"] = run_batch_workload(hy, P, torch)
     if args.serve:
         out["serving"] = run_serving_workload(hy, P, args.serve, args.serve_budget_gb)
 
     print(json.dumps(out), flush=True)
+
+
+def run_small_workload(hy, P, torch, reps=20):
+    """The 32^3 single-MeshBlock eigenmode (10 steps, FP64): time per step with
+    eager launches and replayed from a captured HIP graph (launch-bound size)."""
+    pb, steps = P.workload_eigenmode_32()
+    s = torch.cuda.Stream()
+    g = hy.Problem(pb).set_state(stream=s)
+    g.advance(steps, stream=s)
+    s.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.advance(steps, stream=s)
+    s.synchronize()
+    eager = (time.perf_counter() - t0) / (reps * steps)
+    hy.batch_advance_graph([g], [steps], stream=s)
+    s.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        hy.batch_advance_graph([g], [steps], stream=s)
+    s.synchronize()
+    graph = (time.perf_counter() - t0) / (reps * steps)
+    g.close()
+    return {"workload": "sound-wave eigenmode 32^3, one MeshBlock, FP64, PLM+HLLC",
+            "us_per_step_eager": eager * 1e6, "us_per_step_graph": graph * 1e6,
+            "cell_updates_per_s_graph": pb.cells / graph}
 
 
 def run_batch_workload(hy, P, torch, count=48, seed=3):

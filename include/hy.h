@@ -129,6 +129,19 @@ hy_status hy_advance(hy_problem* p, int32_t nsteps, void* hip_stream);
 hy_status hy_batch_advance(hy_problem* const* ps, const int32_t* nsteps, int32_t n,
                            void* hip_stream);
 
+/* Same as hy_batch_advance, replayed from a captured HIP graph (async).
+ * The first call for a given (problems, nsteps, launch shapes, step parity)
+ * captures the launch sequence on `hip_stream` and instantiates it; later calls
+ * with the same signature replay it with one graph launch, which removes the
+ * per-kernel launch cost for small problems. Every time step stays on the
+ * device, so replays need no host input. The graph holds kernel launches only
+ * (no memset or copy nodes). `hip_stream` must not be the default (NULL)
+ * stream, which cannot be captured. Results are bitwise equal to
+ * hy_batch_advance. Graphs that involve a problem are released by its
+ * hy_destroy; hy_set_launch on a problem also invalidates them. */
+hy_status hy_batch_advance_graph(hy_problem* const* ps, const int32_t* nsteps, int32_t n,
+                                 void* hip_stream);
+
 /* Wait for the problem's last stream, then read its time, the time step the
  * next step will take, the steps taken and the floor hits (any pointer may be
  * NULL). Returns HY_ERR_STATE if the device flagged a bad state. */

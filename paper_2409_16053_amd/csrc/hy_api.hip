@@ -129,8 +129,10 @@ void default_launch(const hy_problem* p, int* variant, int* kc) {
   stage_variant_shape(v, &tx, &ty);
   const int64_t cols = (int64_t)((bx + tx - 1) / tx) * ((p->cfg.block[1] + ty - 1) / ty);
   const int64_t nb = (int64_t)p->nblk[0] * p->nblk[1] * p->nblk[2];
+  // enough tiles to fill the chip several times over; small problems march
+  // through short z-chunks (down to one plane) rather than leave CUs idle
   int k = bz;
-  while (k > 8 && nb * cols * ((bz + k - 1) / k) < 2048) k = (k + 1) / 2;
+  while (k > 1 && nb * cols * ((bz + k - 1) / k) < 2048) k = (k + 1) / 2;
   *variant = v;
   *kc = k;
 }
@@ -240,6 +242,45 @@ hy_status run_batch(hy_problem* const* ps, const int32_t* nsteps, int32_t n, hip
     ps[q]->last = s;
   }
   return HY_OK;
+}
+
+// Captured step sequences, keyed by everything that is baked into them.
+struct GraphKey {
+  std::vector<hy_problem*> ps;
+  std::vector<int32_t> nsteps;
+  std::vector<int32_t> parity, variant, kc;
+  bool operator==(const GraphKey& o) const {
+    return ps == o.ps && nsteps == o.nsteps && parity == o.parity && variant == o.variant &&
+           kc == o.kc;
+  }
+};
+
+struct GraphEntry {
+  GraphKey key;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;  // most recently used last
+constexpr size_t kMaxGraphs = 64;
+
+void release(GraphEntry& g) {
+  (void)hipGraphExecDestroy(g.exec);
+  (void)hipGraphDestroy(g.graph);
+}
+
+void drop_graphs_of(const hy_problem* p) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (size_t i = 0; i < g_graphs.size();) {
+    const auto& v = g_graphs[i].key.ps;
+    if (std::find(v.begin(), v.end(), p) != v.end()) {
+      release(g_graphs[i]);
+      g_graphs.erase(g_graphs.begin() + (long)i);
+    } else {
+      ++i;
+    }
+  }
 }
 
 hy_status read_counters(hy_problem* p, DevCounters* c) {
@@ -384,6 +425,66 @@ hy_status hy_batch_advance(hy_problem* const* ps, const int32_t* nsteps, int32_t
   return run_batch(ps, nsteps, n, (hipStream_t)stream, nullptr, 1);
 }
 
+hy_status hy_batch_advance_graph(hy_problem* const* ps, const int32_t* nsteps, int32_t n,
+                                 void* stream) {
+  hy_status st = check_batch(ps, nsteps, n);
+  if (st != HY_OK) return st;
+  if (!stream) return fail(HY_ERR_ARG, "graph capture needs a non-default stream");
+  if (n == 0) return HY_OK;
+  hipStream_t s = (hipStream_t)stream;
+  GraphKey key;
+  for (int q = 0; q < n; ++q) {
+    key.ps.push_back(ps[q]);
+    key.nsteps.push_back(nsteps[q]);
+    key.parity.push_back((int32_t)(ps[q]->steps & 1));
+    key.variant.push_back(ps[q]->variant);
+    key.kc.push_back(ps[q]->kc);
+  }
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (size_t i = 0; i < g_graphs.size(); ++i) {
+    if (g_graphs[i].key == key) {
+      GraphEntry e = g_graphs[i];
+      g_graphs.erase(g_graphs.begin() + (long)i);
+      g_graphs.push_back(e);
+      HY_HIP(hipGraphLaunch(e.exec, s));
+      for (int q = 0; q < n; ++q) {
+        ps[q]->steps += nsteps[q];
+        ps[q]->last = s;
+      }
+      return HY_OK;
+    }
+  }
+  std::vector<int64_t> before(n);
+  for (int q = 0; q < n; ++q) before[q] = ps[q]->steps;
+  HY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  st = run_batch(ps, nsteps, n, s, nullptr, 1);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &graph);
+  for (int q = 0; q < n; ++q) ps[q]->steps = before[q];  // nothing ran yet
+  if (st != HY_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail(HY_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(HY_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  if (g_graphs.size() >= kMaxGraphs) {
+    release(g_graphs.front());
+    g_graphs.erase(g_graphs.begin());
+  }
+  g_graphs.push_back(GraphEntry{key, graph, exec});
+  HY_HIP(hipGraphLaunch(exec, s));
+  for (int q = 0; q < n; ++q) {
+    ps[q]->steps += nsteps[q];
+    ps[q]->last = s;
+  }
+  return HY_OK;
+}
+
 hy_status hy_query(hy_problem* p, double* t, double* dt_next, int64_t* steps, int64_t* floor_hits) {
   if (!p) return fail(HY_ERR_ARG, "NULL problem");
   DevCounters c;
@@ -411,6 +512,7 @@ hy_status hy_set_time(hy_problem* p, double t) {
 hy_status hy_destroy(hy_problem* p) {
   if (!p) return HY_OK;
   hipError_t e = hipStreamSynchronize(p->last);
+  drop_graphs_of(p);
   delete p;
   if (e != hipSuccess) return fail(HY_ERR_HIP, hipGetErrorString(e));
   return HY_OK;
@@ -435,6 +537,7 @@ hy_status hy_set_launch(hy_problem* p, int32_t variant, int32_t kc) {
     return fail(HY_ERR_ARG, "bad launch shape");
   p->variant = variant;
   p->kc = std::min(kc, p->cfg.block[2]);
+  drop_graphs_of(p);
   return HY_OK;
 }
 
@@ -451,8 +554,8 @@ hy_status hy_autotune(hy_problem* p, void* stream, int32_t full_steps, int32_t* 
   hipStream_t s = (hipStream_t)stream;
   const int bz = p->cfg.block[2];
   std::vector<int> kcs;
-  for (int k : {bz, bz / 2, bz / 4, 32, 16, 8})
-    if (k >= 4 && k <= bz && std::find(kcs.begin(), kcs.end(), k) == kcs.end()) kcs.push_back(k);
+  for (int k : {bz, bz / 2, bz / 4, 32, 16, 8, 4, 2, 1})
+    if (k >= 1 && k <= bz && std::find(kcs.begin(), kcs.end(), k) == kcs.end()) kcs.push_back(k);
   if (kcs.empty()) kcs.push_back(bz);
   hipEvent_t e0, e1;
   HY_HIP(hipEventCreate(&e0));

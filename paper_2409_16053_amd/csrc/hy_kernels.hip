@@ -47,7 +47,22 @@ __device__ __forceinline__ double rcp(double x) {
   return fma(r, e, r);
 }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rsqrt_(double x) { return sqrt(x); }
+
+// Square root. FP64: the hardware reciprocal-square-root estimate, one
+// Goldschmidt step (g ~ sqrt(x), h ~ 1/(2 sqrt(x)); the error is squared) and
+// a final Newton correction of g (squared again), which lands within an ulp;
+// x == 0 gives 0. Arguments here are sound-speed-like quantities >= 0. FP32:
+// the native instruction.
+__device__ __forceinline__ double rsqrt_(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  return x == 0.0 ? 0.0 : g;
+}
 __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // XCD-aware remap: the dispatcher hands workgroup w to XCD w % 8. Give each
@@ -192,7 +207,7 @@ __device__ __forceinline__ double cell_dt(const Floors& fl, double gamma, double
   double w[5];
   int h = 0, b = 0;
   c2p(fl, u, w, h, b);
-  const double cs = sqrt(gamma * (gm1 * w[4]) * rcp(w[0]));
+  const double cs = rsqrt_(gamma * (gm1 * w[4]) * rcp(w[0]));
   double m = dx[0] * rcp(fabs(w[1]) + cs);
   m = fmin(m, dx[1] * rcp(fabs(w[2]) + cs));
   m = fmin(m, dx[2] * rcp(fabs(w[3]) + cs));

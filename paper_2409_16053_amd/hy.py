@@ -54,6 +54,7 @@ SIGNATURES = {
     "hy_get_state": ([_vp, _vp, _c.c_int, _vp], _c.c_int),
     "hy_advance": ([_vp, _c.c_int32, _vp], _c.c_int),
     "hy_batch_advance": ([_c.POINTER(_vp), _i32p, _c.c_int32, _vp], _c.c_int),
+    "hy_batch_advance_graph": ([_c.POINTER(_vp), _i32p, _c.c_int32, _vp], _c.c_int),
     "hy_query": ([_vp, _dp, _dp, _i64p, _i64p], _c.c_int),
     "hy_set_time": ([_vp, _c.c_double], _c.c_int),
     "hy_destroy": ([_vp], _c.c_int),
@@ -293,6 +294,17 @@ def batch_advance(problems, nsteps, stream=None):
         nsteps = [int(nsteps)] * n
     ns = (_c.c_int32 * n)(*[int(x) for x in nsteps])
     _check(lib().hy_batch_advance(hs, ns, n, _stream(stream)))
+
+
+def batch_advance_graph(problems, nsteps, stream):
+    """Like ``batch_advance`` but captured once into a HIP graph and replayed
+    (``stream`` must be a non-default torch.cuda.Stream)."""
+    n = len(problems)
+    hs = (_vp * n)(*[p.h for p in problems])
+    if np.isscalar(nsteps):
+        nsteps = [int(nsteps)] * n
+    ns = (_c.c_int32 * n)(*[int(x) for x in nsteps])
+    _check(lib().hy_batch_advance_graph(hs, ns, n, _stream(stream)))
 
 
 def copy_probe(dst, src, nbytes=None, stream=None):
