@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
         ("n", ctypes.c_int32 * 3),
         ("bc", (ctypes.c_int32 * 2) * 3),
         ("recon", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("fofc", ctypes.c_int32),
         ("dx", ctypes.c_double * 3),
         ("gamma", ctypes.c_double),
         ("cfl", ctypes.c_double),
@@ -48,7 +48,8 @@ class Params(ctypes.Structure):
 def _bind(L):
     dp = ctypes.POINTER(ctypes.c_double)
     pp = ctypes.POINTER(Params)
-    L.or_advance.argtypes = [pp, dp, ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_longlong)]
+    L.or_advance.argtypes = [pp, dp, ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_longlong),
+                             ctypes.POINTER(ctypes.c_longlong)]
     L.or_advance.restype = ctypes.c_int
     L.or_new_dt.argtypes = [pp, dp]
     L.or_new_dt.restype = ctypes.c_double
@@ -64,6 +65,8 @@ def _bind(L):
     L.or_ppm4_cell.restype = None
     L.or_hllc.argtypes = [ctypes.c_double, dp, dp, dp]
     L.or_hllc.restype = None
+    L.or_llf.argtypes = [ctypes.c_double, dp, dp, dp]
+    L.or_llf.restype = None
     L.or_nghost.argtypes = [ctypes.c_int]
     L.or_nghost.restype = ctypes.c_int
     L.or_set_threads.argtypes = [ctypes.c_int]
@@ -98,6 +101,7 @@ def params(pb) -> Params:
         P.bc[d][1] = int(pb.bc[d][1])
         P.dx[d] = float(pb.dx[d])
     P.recon = int(pb.recon)
+    P.fofc = int(getattr(pb, "fofc", 0))
     P.gamma = float(pb.gamma)
     P.cfl = float(pb.cfl)
     P.rho_floor = float(pb.rho_floor)
@@ -142,9 +146,11 @@ class Oracle:
         tt = ctypes.c_double(t)
         dd = ctypes.c_double(dt)
         fh = ctypes.c_longlong(0)
+        fc = ctypes.c_longlong(0)
         st = self._L.or_advance(ctypes.byref(P), _dp(U), int(nsteps), ctypes.byref(tt),
-                              ctypes.byref(dd), ctypes.byref(fh))
-        return dict(U=U, t=tt.value, dt=dd.value, floor_hits=fh.value, status=st)
+                                ctypes.byref(dd), ctypes.byref(fh), ctypes.byref(fc))
+        return dict(U=U, t=tt.value, dt=dd.value, floor_hits=fh.value, fofc_cells=fc.value,
+                    status=st)
 
     def divergence(self, pb, U=None):
         U = np.ascontiguousarray(pb.U if U is None else U, dtype=np.float64)
@@ -183,6 +189,14 @@ class Oracle:
         r = ctypes.c_double()
         self._L.or_ppm4_cell(_dp(w), ctypes.byref(l), ctypes.byref(r))
         return l.value, r.value
+
+    def llf(self, gamma, wl, wr):
+        """LLF flux for primitive states [rho, u_n, u_t1, u_t2, p]."""
+        a = np.ascontiguousarray(wl, dtype=np.float64)
+        b = np.ascontiguousarray(wr, dtype=np.float64)
+        f = np.empty(5)
+        self._L.or_llf(float(gamma), _dp(a), _dp(b), _dp(f))
+        return f
 
     def hllc(self, gamma, wl, wr):
         """HLLC flux for primitive states [rho, u_n, u_t1, u_t2, p]."""
@@ -241,3 +255,7 @@ def ppm4_cell(w5):
 
 def hllc(gamma, wl, wr):
     return _inst().hllc(gamma, wl, wr)
+
+
+def llf(gamma, wl, wr):
+    return _inst().llf(gamma, wl, wr)

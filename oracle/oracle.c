@@ -48,7 +48,7 @@ typedef struct {
   int32_t n[3];      /* interior cells nx, ny, nz                      */
   int32_t bc[3][2];  /* per axis (lower, upper): OR_PERIODIC/OR_OUTFLOW */
   int32_t recon;     /* OR_PLM (2 ghosts) or OR_PPM4 (3 ghosts)        */
-  int32_t pad_;
+  int32_t fofc;      /* 1: first-order flux correction in every stage  */
   double dx[3];      /* cell widths                                    */
   double gamma;      /* ratio of specific heats, > 1                   */
   double cfl;        /* Courant number                                 */
@@ -271,6 +271,38 @@ void or_hllc(double gamma, const double wl[5], const double wr[5], double f[5]) 
 }
 
 /* ------------------------------------------------------------------------
+ * Local Lax-Friedrichs (Rusanov) flux (Sec. 3 names LLF; Toro's textbook):
+ * the mean of the two physical fluxes minus half the largest local signal
+ * speed a = max(|u_L| + c_L, |u_R| + c_R) times the jump in U. Same state and
+ * flux ordering as or_hllc.
+ * ---------------------------------------------------------------------- */
+void or_llf(double gamma, const double wl[5], const double wr[5], double f[5]) {
+  const double gm1 = gamma - 1.0;
+  double ul[5], ur[5], fl[5], fr[5];
+  const double* w[2] = {wl, wr};
+  double* uu[2] = {ul, ur};
+  double* ff[2] = {fl, fr};
+  double a = 0.0;
+  for (int s = 0; s < 2; ++s) {
+    const double r = w[s][0], un = w[s][1], v1 = w[s][2], v2 = w[s][3], pr = w[s][4];
+    const double e = pr / gm1 + 0.5 * r * (un * un + v1 * v1 + v2 * v2);
+    uu[s][0] = r;
+    uu[s][1] = r * un;
+    uu[s][2] = r * v1;
+    uu[s][3] = r * v2;
+    uu[s][4] = e;
+    ff[s][0] = r * un;
+    ff[s][1] = r * un * un + pr;
+    ff[s][2] = r * un * v1;
+    ff[s][3] = r * un * v2;
+    ff[s][4] = un * (e + pr);
+    const double sp = fabs(un) + sqrt(gamma * pr / r);
+    if (sp > a) a = sp;
+  }
+  for (int q = 0; q < 5; ++q) f[q] = 0.5 * (fl[q] + fr[q]) - 0.5 * a * (ur[q] - ul[q]);
+}
+
+/* ------------------------------------------------------------------------
  * One stage's flux divergence L(U) on interior cells (method of lines).
  * ---------------------------------------------------------------------- */
 typedef struct {
@@ -336,20 +368,24 @@ static void face_states(const or_params* p, const work* w, int d, int i, int j, 
 }
 
 /* Riemann flux at one face along d: rotate so the normal velocity comes
- * first, form p = (gamma-1) u_g, solve, rotate back into (Mx, My, Mz). */
+ * first, form p = (gamma-1) u_g, solve (HLLC, or LLF when llf != 0), rotate
+ * back into (Mx, My, Mz). */
 static void face_flux(const or_params* p, int d, const double wl[5], const double wr[5],
-                      double out[5]) {
+                      double out[5], int llf) {
   const int n = 1 + d, t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
   double ql[5] = {wl[0], wl[n], wl[t1], wl[t2], (p->gamma - 1.0) * wl[4]};
   double qr[5] = {wr[0], wr[n], wr[t1], wr[t2], (p->gamma - 1.0) * wr[4]};
   double f[5];
-  or_hllc(p->gamma, ql, qr, f);
+  if (llf) or_llf(p->gamma, ql, qr, f);
+  else or_hllc(p->gamma, ql, qr, f);
   out[0] = f[0];
   out[n] = f[1];
   out[t1] = f[2];
   out[t2] = f[3];
   out[4] = f[4];
 }
+
+static void flux_divergence(const or_params* p, work* w);
 
 /* L(U) for the interior state Uin[5][nz][ny][nx]. Returns floor hits on
  * interior cells; sets *bad if any interior cell is unrecoverable. */
@@ -395,12 +431,21 @@ static long long divergence(const or_params* p, work* w, const double* Uin, int*
         for (int i = 0; i < fx; ++i) {
           double wl[5], wr[5], f[5];
           face_states(p, w, d, i, j, k, wl, wr);
-          face_flux(p, d, wl, wr, f);
+          face_flux(p, d, wl, wr, f, 0);
           for (int v = 0; v < 5; ++v) w->F[d][(size_t)v * w->fsv[d] + ((size_t)k * fy + j) * fx + i] = f[v];
         }
   }
 
-  /* L = -(Fx+ - Fx-)/dx - (Fy+ - Fy-)/dy - (Fz+ - Fz-)/dz, summed x, y, z */
+  flux_divergence(p, w);
+  if (bad) *bad = anybad;
+  return hits;
+}
+
+/* L = -(Fx+ - Fx-)/dx - (Fy+ - Fy-)/dy - (Fz+ - Fz-)/dz, summed x, y, z,
+ * from the face fluxes held in w->F. */
+static void flux_divergence(const or_params* p, work* w) {
+  const int nx = p->n[0], ny = p->n[1], nz = p->n[2];
+  const size_t nc = ncell(p);
   for (int v = 0; v < 5; ++v) {
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < nz; ++k)
@@ -418,8 +463,6 @@ static long long divergence(const or_params* p, work* w, const double* Uin, int*
           w->L[v * nc + lin(p, i, j, k)] = l;
         }
   }
-  if (bad) *bad = anybad;
-  return hits;
 }
 
 /* ------------------------------------------------------------------------
@@ -445,16 +488,89 @@ double or_new_dt(const or_params* p, const double* U) {
 }
 
 /* ------------------------------------------------------------------------
+ * The stage update, then first-order flux correction (FOFC, Sec. 3): if the
+ * updated density or pressure of an interior cell is not positive, the fluxes
+ * on all faces of that cell are replaced by LLF fluxes of the first-order
+ * (piecewise-constant) states -- the primitives of the two cells sharing the
+ * face -- and the stage update is recomputed with the corrected fluxes.
+ * Stage 1: Uout = Ust + h L.  Stage 2: Uout = U0/2 + Ust/2 + h L/2.
+ * Returns the number of corrected cells.
+ * ---------------------------------------------------------------------- */
+static void stage_formula(const or_params* p, const work* w, int stage, const double* U0,
+                          const double* Ust, double h, double* Uout) {
+  const size_t nt = 5 * ncell(p);
+  if (stage == 1) {
+#pragma omp parallel for schedule(static)
+    for (size_t c = 0; c < nt; ++c) Uout[c] = Ust[c] + h * w->L[c];
+  } else {
+#pragma omp parallel for schedule(static)
+    for (size_t c = 0; c < nt; ++c) Uout[c] = 0.5 * U0[c] + 0.5 * Ust[c] + 0.5 * h * w->L[c];
+  }
+}
+
+static long long stage_apply(const or_params* p, work* w, int stage, const double* U0,
+                             const double* Ust, double h, double* Uout) {
+  stage_formula(p, w, stage, U0, Ust, h, Uout);
+  if (!p->fofc) return 0;
+  const int nx = p->n[0], ny = p->n[1], nz = p->n[2];
+  const size_t nc = ncell(p);
+  long long flagged = 0;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const size_t c = lin(p, i, j, k);
+        const double r = Uout[c], mx = Uout[nc + c], my = Uout[2 * nc + c];
+        const double mz = Uout[3 * nc + c], e = Uout[4 * nc + c];
+        const double pr = (p->gamma - 1.0) * (e - 0.5 * (mx * mx + my * my + mz * mz) / r);
+        if (r > 0.0 && pr > 0.0) continue;
+        ++flagged;
+        /* replace the six face fluxes of this cell */
+        for (int d = 0; d < 3; ++d) {
+          const int di = d == 0, dj = d == 1, dk = d == 2;
+          const int fx = nx + di, fy = ny + dj;
+          for (int side = 0; side < 2; ++side) {
+            /* face between cells (c-1, c) for side 0 and (c, c+1) for side 1 */
+            const int li = i - di * (1 - side), lj = j - dj * (1 - side), lk = k - dk * (1 - side);
+            double wl[5], wr[5], f[5];
+            for (int v = 0; v < 5; ++v) {
+              wl[v] = w->W[at(&w->G, v, li, lj, lk)];
+              wr[v] = w->W[at(&w->G, v, li + di, lj + dj, lk + dk)];
+            }
+            face_flux(p, d, wl, wr, f, 1);
+            const int fi = i + di * side, fj = j + dj * side, fk = k + dk * side;
+            for (int v = 0; v < 5; ++v)
+              w->F[d][(size_t)v * w->fsv[d] + ((size_t)fk * fy + fj) * fx + fi] = f[v];
+            /* on a periodic axis the faces 0 and n are one face stored twice */
+            const int fn = d == 0 ? fi : (d == 1 ? fj : fk);
+            if (p->bc[d][0] == OR_PERIODIC && (fn == 0 || fn == p->n[d])) {
+              const int tw = fn == 0 ? p->n[d] : 0;
+              const int ti = d == 0 ? tw : fi, tj = d == 1 ? tw : fj, tk = d == 2 ? tw : fk;
+              for (int v = 0; v < 5; ++v)
+                w->F[d][(size_t)v * w->fsv[d] + ((size_t)tk * fy + tj) * fx + ti] = f[v];
+            }
+          }
+        }
+      }
+  if (flagged) {
+    flux_divergence(p, w);
+    stage_formula(p, w, stage, U0, Ust, h, Uout);
+  }
+  return flagged;
+}
+
+/* ------------------------------------------------------------------------
  * Advance U[5][nz][ny][nx] by nsteps SSP-RK2 steps (Sec. 3, method of lines,
  * low-storage SSP-RK of Ketcheson 2010, two stages):
  *   U1      = Un + dt L(Un)
  *   U(n+1)  = Un/2 + U1/2 + dt L(U1)/2
- * then dt for the next step from U(n+1). *dt carries the step size in and the
- * next one out; *t and *floor_hits accumulate. Returns OR_ERR_STATE when an
- * interior cell held a non-finite value or rho <= 0 (the step still runs).
+ * (each stage followed by FOFC when enabled), then dt for the next step from
+ * U(n+1). *dt carries the step size in and the next one out; *t,
+ * *floor_hits and *fofc_cells accumulate (either counter may be NULL).
+ * Returns OR_ERR_STATE when an interior cell held a non-finite value or
+ * rho <= 0 (the step still runs).
  * ---------------------------------------------------------------------- */
 int or_advance(const or_params* p, double* U, int nsteps, double* t, double* dt,
-               long long* floor_hits) {
+               long long* floor_hits, long long* fofc_cells) {
   if (!p || !U || !t || !dt || nsteps < 0) return OR_ERR_ARG;
   for (int d = 0; d < 3; ++d) {
     if (p->n[d] < 1) return OR_ERR_ARG;
@@ -464,25 +580,27 @@ int or_advance(const or_params* p, double* U, int nsteps, double* t, double* dt,
   if (work_alloc(&w, p) != OR_OK) { work_free(&w); return OR_ERR_NOMEM; }
   const size_t nt = 5 * ncell(p);
   double* U1 = malloc(nt * sizeof(double));
-  if (!U1) { work_free(&w); return OR_ERR_NOMEM; }
+  double* U2 = malloc(nt * sizeof(double));
+  if (!U1 || !U2) { free(U1); free(U2); work_free(&w); return OR_ERR_NOMEM; }
   int status = OR_OK;
-  long long hits = 0;
+  long long hits = 0, fofc = 0;
   for (int s = 0; s < nsteps; ++s) {
     const double h = *dt;
     int bad = 0;
     hits += divergence(p, &w, U, &bad);
     if (bad) status = OR_ERR_STATE;
-#pragma omp parallel for schedule(static)
-    for (size_t c = 0; c < nt; ++c) U1[c] = U[c] + h * w.L[c];
+    fofc += stage_apply(p, &w, 1, U, U, h, U1);
     hits += divergence(p, &w, U1, &bad);
     if (bad) status = OR_ERR_STATE;
-#pragma omp parallel for schedule(static)
-    for (size_t c = 0; c < nt; ++c) U[c] = 0.5 * U[c] + 0.5 * U1[c] + 0.5 * h * w.L[c];
+    fofc += stage_apply(p, &w, 2, U, U1, h, U2);
+    memcpy(U, U2, nt * sizeof(double));
     *t += h;
     *dt = or_new_dt(p, U);
   }
   if (floor_hits) *floor_hits += hits;
+  if (fofc_cells) *fofc_cells += fofc;
   free(U1);
+  free(U2);
   work_free(&w);
   return status;
 }

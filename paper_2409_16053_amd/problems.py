@@ -51,6 +51,7 @@ class Problem:
     block: tuple | None = None    # MeshBlock interior size (bx, by, bz)
     rho_floor: float = 1e-10
     p_floor: float = 1e-13
+    fofc: int = 0                 # first-order flux correction (Sec. 3) on/off
     name: str = ""
     meta: dict = field(default_factory=dict)
 

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+import test_oracle_fofc as fofc
 import test_oracle_physics as phys
 import test_oracle_units as units
 from paper_2409_16053_amd import problems as P
@@ -35,8 +36,8 @@ MUTANTS = [
      "l -= (Fy[ym + nx] - Fy[ym]) / p->dx[0];"),
     ("divergence_sign", "l -= (Fz[zm + (size_t)nx * ny] - Fz[zm]) / p->dx[2];",
      "l += (Fz[zm + (size_t)nx * ny] - Fz[zm]) / p->dx[2];"),
-    ("rk2_stage2_weight", "0.5 * U[c] + 0.5 * U1[c] + 0.5 * h * w.L[c]",
-     "0.5 * U[c] + 0.5 * U1[c] + h * w.L[c]"),
+    ("rk2_stage2_weight", "0.5 * U0[c] + 0.5 * Ust[c] + 0.5 * h * w->L[c]",
+     "0.5 * U0[c] + 0.5 * Ust[c] + h * w->L[c]"),
     ("ghost_periodic_offset", "return bchi == OR_PERIODIC ? c % n : n - 1;",
      "return bchi == OR_PERIODIC ? (c + 1) % n : n - 1;"),
     ("ghost_outflow_index", "return bclo == OR_PERIODIC ? ((c % n) + n) % n : 0;",
@@ -45,6 +46,9 @@ MUTANTS = [
     ("dt_signed_velocity", "p->dx[d] / (fabs(q[1 + d]) + cs)", "p->dx[d] / (q[1 + d] + cs)"),
     ("dt_sound_speed_gamma", "sqrt(p->gamma * pr / q[0])", "sqrt(pr / q[0])"),
     ("face_state_shift", "s[o + 2] = w->W[at(G, v, i + o * di", "s[o + 2] = w->W[at(G, v, i + (o + 1) * di"),
+    ("llf_dissipation_sign", "0.5 * (fl[q] + fr[q]) - 0.5 * a * (ur[q] - ul[q])",
+     "0.5 * (fl[q] + fr[q]) + 0.5 * a * (ur[q] - ul[q])"),
+    ("fofc_wrong_cell_side", "const int li = i - di * (1 - side)", "const int li = i - di * side"),
 ]
 
 
@@ -79,6 +83,8 @@ def _fast_pins(O):
     yield lambda: phys.test_sod_axis_symmetry_bitwise(O, P.PLM)
     yield lambda: phys.test_colliding_streams_two_shocks(O, P.PLM)
     yield lambda: phys.test_shear_wave_advection(O, 0)
+    yield lambda: fofc.test_llf_is_hll_with_symmetric_speeds(O, 1.4)
+    yield lambda: fofc.test_fofc_restores_positivity_hypersonic_turbulence(O, P.PLM)
 
 
 def test_unplanted_build_passes_fast_pins(tmp_path):
