@@ -67,6 +67,11 @@ enum { HY_FP64 = 0, HY_MIXED = 1 };
  *  precision   HY_FP64 (all arithmetic in FP64) or HY_MIXED (reconstruction
  *              and the Riemann solve in FP32; cons-to-prim, flux divergence,
  *              the RK accumulation and the time step in FP64; U stays FP64).
+ *  fofc        1: first-order flux correction in every RK stage (Sec. 3):
+ *              a cell whose updated density or pressure is not positive has
+ *              the fluxes on all its faces replaced by LLF fluxes of the
+ *              first-order states and its stage update recomputed; 0: off.
+ *              Adds 4 bytes per cell to the workspace.
  *  rho_floor, p_floor  floors applied to the primitive state only (U is
  *              never modified by a floor); each firing is counted.          */
 typedef struct {
@@ -78,12 +83,14 @@ typedef struct {
   double cfl;
   int32_t recon;
   int32_t precision;
+  int32_t fofc;
   double rho_floor, p_floor;
 } hy_config;
 
 /* Device bytes one problem needs: two FP64 state registers of 5 x cells
- * doubles each (the step-start state and the RK stage state) plus a 512-byte
- * header. Returns 0 for an invalid configuration. */
+ * doubles each (the step-start state and the RK stage state), a 512-byte
+ * header, and with fofc one 32-bit tag per cell. Returns 0 for an invalid
+ * configuration. */
 size_t hy_workspace_bytes(const hy_config* cfg);
 
 /* Create a problem in the caller's device workspace `dev_ws` (256-byte
@@ -143,10 +150,11 @@ hy_status hy_batch_advance_graph(hy_problem* const* ps, const int32_t* nsteps, i
                                  void* hip_stream);
 
 /* Wait for the problem's last stream, then read its time, the time step the
- * next step will take, the steps taken and the floor hits (any pointer may be
- * NULL). Returns HY_ERR_STATE if the device flagged a bad state. */
+ * next step will take, the steps taken, the floor hits and the cells corrected
+ * by FOFC (summed over stages; any pointer may be NULL). Returns HY_ERR_STATE
+ * if the device flagged a bad state. */
 hy_status hy_query(hy_problem* p, double* t, double* dt_next, int64_t* steps,
-                   int64_t* floor_hits);
+                   int64_t* floor_hits, int64_t* fofc_cells);
 
 /* Set the simulation time (for resuming from a stored state). */
 hy_status hy_set_time(hy_problem* p, double t);

@@ -63,6 +63,7 @@ bool validate(const hy_config* c, std::string& msg) {
   if (!c) { msg = "config is NULL"; return false; }
   if (c->recon != HY_PLM && c->recon != HY_PPM4) { msg = "recon must be HY_PLM or HY_PPM4"; return false; }
   if (c->precision != HY_FP64 && c->precision != HY_MIXED) { msg = "precision must be HY_FP64 or HY_MIXED"; return false; }
+  if (c->fofc != 0 && c->fofc != 1) { msg = "fofc must be 0 or 1"; return false; }
   const int ng = ghost_depth(c->recon);
   for (int d = 0; d < 3; ++d) {
     if (c->n[d] < 1 || c->block[d] < 1) { msg = "n and block must be >= 1"; return false; }
@@ -92,6 +93,10 @@ bool validate(const hy_config* c, std::string& msg) {
 
 size_t reg_bytes(const hy_config* c) {
   return align256((size_t)c->n[0] * c->n[1] * c->n[2] * 5 * sizeof(double));
+}
+
+size_t tag_bytes(const hy_config* c) {
+  return c->fofc ? align256((size_t)c->n[0] * c->n[1] * c->n[2] * sizeof(uint32_t)) : 0;
 }
 
 // Tuned launch shapes per (block size, recon, precision).
@@ -197,12 +202,37 @@ hy_status launch_group(hy_problem* const* ps, const std::vector<int>& act, const
       e.ntz = (p->cfg.block[2] + e.kc - 1) / e.kc;
       e.parity = (int32_t)(step_of[q] & 1);
       e.flags = flags;
+      e.tag = (uint32_t)(2 * step_of[q] + stage);
       tiles += (int64_t)p->nblk[0] * p->nblk[1] * p->nblk[2] * e.ntx * e.nty * e.ntz;
     }
     if (tiles > 0x7fffffff) return fail(HY_ERR_ARG, "too many tiles in one launch");
     a.ntiles = (int32_t)tiles;
     if (tiles == 0) continue;
     HY_HIP(launch_stage(pl.variant, pl.recon, pl.prec, stage, a, (int)tiles, s));
+  }
+  return HY_OK;
+}
+
+// First-order flux correction after a stage for the problems that enable it.
+hy_status launch_fix(hy_problem* const* ps, const std::vector<int>& act, const Plan& pl, int stage,
+                     const std::vector<int64_t>& step_of, hipStream_t s) {
+  std::vector<int> f;
+  for (int q : act)
+    if (ps[q]->cfg.fofc) f.push_back(q);
+  for (size_t c0 = 0; c0 < f.size(); c0 += kMaxBatch) {
+    FixArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.stage = stage;
+    int grid = 1;
+    for (size_t c = c0; c < std::min(f.size(), c0 + (size_t)kMaxBatch); ++c) {
+      const hy_problem* p = ps[f[c]];
+      FixEntry& e = a.e[a.nprob++];
+      e.p = p->dp;
+      e.tag = (uint32_t)(2 * step_of[f[c]] + stage);
+      e.parity = (int32_t)(step_of[f[c]] & 1);
+      grid = std::max(grid, fofc_grid(p->hp.nblocks, p->cfg.block[2]));
+    }
+    HY_HIP(launch_fofc(pl.recon, pl.prec, a, std::min(grid, 65535), s));
   }
   return HY_OK;
 }
@@ -230,6 +260,8 @@ hy_status run_batch(hy_problem* const* ps, const int32_t* nsteps, int32_t n, hip
         for (int q : pl.idx)
           if (nsteps[q] > k) act.push_back(q);
         st = launch_group(ps, act, pl, stage, step_of, flags, s);
+        if (st != HY_OK) return st;
+        st = launch_fix(ps, act, pl, stage, step_of, s);
         if (st != HY_OK) return st;
       }
       if (ev) HY_HIP(hipEventRecord((*ev)[evi++], s));
@@ -299,7 +331,7 @@ size_t hy_workspace_bytes(const hy_config* cfg) {
     g_err = msg;
     return 0;
   }
-  return (size_t)kHeaderBytes + 2 * reg_bytes(cfg);
+  return (size_t)kHeaderBytes + 2 * reg_bytes(cfg) + tag_bytes(cfg);
 }
 
 hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_problem** out) {
@@ -358,6 +390,10 @@ hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_prob
   h.cfl = cfg->cfl;
   h.rho_floor = cfg->rho_floor;
   h.p_floor = cfg->p_floor;
+  h.fofc = cfg->fofc;
+  h.tags = cfg->fofc ? (uint32_t*)(p->ws + kHeaderBytes + 2 * reg_bytes(cfg)) : nullptr;
+  h.fofc_cnt = p->dc->fofc_cnt;
+  h.fofc_total = &p->dc->fofc_total;
 
   unsigned char hdr[kHeaderBytes];
   std::memset(hdr, 0, sizeof hdr);
@@ -366,7 +402,8 @@ hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_prob
   std::memset(&c, 0, sizeof c);
   c.dtmin[0] = c.dtmin[1] = kInf;
   std::memcpy(hdr + sizeof(DevProblem), &c, sizeof c);
-  if (hipMemcpy(p->ws, hdr, sizeof hdr, hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMemcpy(p->ws, hdr, sizeof hdr, hipMemcpyHostToDevice) != hipSuccess ||
+      (cfg->fofc && hipMemset(h.tags, 0, tag_bytes(cfg)) != hipSuccess)) {
     delete p;
     return fail(HY_ERR_HIP, "header upload failed");
   }
@@ -485,7 +522,8 @@ hy_status hy_batch_advance_graph(hy_problem* const* ps, const int32_t* nsteps, i
   return HY_OK;
 }
 
-hy_status hy_query(hy_problem* p, double* t, double* dt_next, int64_t* steps, int64_t* floor_hits) {
+hy_status hy_query(hy_problem* p, double* t, double* dt_next, int64_t* steps, int64_t* floor_hits,
+                   int64_t* fofc_cells) {
   if (!p) return fail(HY_ERR_ARG, "NULL problem");
   DevCounters c;
   hy_status st = read_counters(p, &c);
@@ -498,6 +536,7 @@ hy_status hy_query(hy_problem* p, double* t, double* dt_next, int64_t* steps, in
   }
   if (steps) *steps = p->steps;
   if (floor_hits) *floor_hits = (int64_t)c.floor_hits;
+  if (fofc_cells) *fofc_cells = (int64_t)(c.fofc_total + c.fofc_cnt[0] + c.fofc_cnt[1]);
   if (c.err) return fail(HY_ERR_STATE, "non-finite state or rho <= 0 seen on the device");
   return HY_OK;
 }

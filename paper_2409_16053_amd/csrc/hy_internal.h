@@ -32,6 +32,10 @@ struct DevProblem {
   int64_t bstride;           // doubles per block (5 * vstride)
   double dx[3];
   double gamma, cfl, rho_floor, p_floor;
+  uint32_t* tags;            // per-cell FOFC tag (cell flagged in stage `tag`)
+  unsigned long long* fofc_cnt;  // [2] cells flagged in the stages of tag parity 0/1
+  unsigned long long* fofc_total;
+  int32_t fofc;              // 1: first-order flux correction enabled
 };
 
 // Counters that follow the descriptor in the header.
@@ -39,6 +43,8 @@ struct DevCounters {
   unsigned long long dtmin[2];
   double time;
   unsigned long long floor_hits;
+  unsigned long long fofc_cnt[2];
+  unsigned long long fofc_total;
   unsigned int err;
   unsigned int pad;
 };
@@ -52,7 +58,8 @@ struct BatchEntry {
   int32_t ntx, nty, ntz;  // tiles per block along x, y, z
   int32_t kc;       // planes per z-chunk
   int32_t parity;   // step index mod 2: which dtmin slot the step reads
-  int32_t flags;    // bit 0: count floors and flag bad states
+  int32_t flags;    // bit 0: count floors, flag bad states, flag FOFC cells
+  uint32_t tag;     // 2 * step + stage: FOFC tag of this stage (never 0)
 };
 
 struct StageArgs {
@@ -61,6 +68,21 @@ struct StageArgs {
   BatchEntry e[kMaxBatch];
 };
 
-static_assert(sizeof(StageArgs) <= 2048, "kernel arguments too large");
+static_assert(sizeof(StageArgs) <= 3072, "kernel arguments too large");
+
+// First-order flux correction pass after a stage (problems with fofc on).
+struct FixEntry {
+  const DevProblem* p;
+  uint32_t tag;
+  int32_t parity;
+};
+
+struct FixArgs {
+  int32_t nprob;
+  int32_t stage;
+  FixEntry e[kMaxBatch];
+};
+
+static_assert(sizeof(FixArgs) <= 3072, "kernel arguments too large");
 
 }  // namespace hy

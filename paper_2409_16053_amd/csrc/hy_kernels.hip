@@ -171,6 +171,24 @@ __device__ __forceinline__ void hllc(const Gas<T>& g, T rl, T ul, T vl, T wl, T 
   f[4] = direct ? fk4 : fk4 + sk * (us4 - ek);
 }
 
+// Local Lax-Friedrichs flux, same state and flux ordering as hllc(): the mean
+// of the physical fluxes minus half the largest signal speed
+// max(|u_L| + c_L, |u_R| + c_R) times the jump in the conserved state.
+template <typename T>
+__device__ __forceinline__ void llf(const Gas<T>& g, T rl, T ul, T vl, T wl, T ugl, T rr, T ur,
+                                    T vr, T wr, T ugr, T f[5]) {
+  const T pl = g.gm1 * ugl, pr = g.gm1 * ugr;
+  const T el = ugl + T(0.5) * rl * ((ul * ul + vl * vl) + wl * wl);
+  const T er = ugr + T(0.5) * rr * ((ur * ur + vr * vr) + wr * wr);
+  const T a = fmax(fabs(ul) + rsqrt_(g.gamma * pl * rcp(rl)), fabs(ur) + rsqrt_(g.gamma * pr * rcp(rr)));
+  const T ml = rl * ul, mr = rr * ur;
+  f[0] = T(0.5) * (ml + mr) - T(0.5) * a * (rr - rl);
+  f[1] = T(0.5) * ((ml * ul + pl) + (mr * ur + pr)) - T(0.5) * a * (mr - ml);
+  f[2] = T(0.5) * (ml * vl + mr * vr) - T(0.5) * a * (rr * vr - rl * vl);
+  f[3] = T(0.5) * (ml * wl + mr * wr) - T(0.5) * a * (rr * wr - rl * wl);
+  f[4] = T(0.5) * (ul * (el + pl) + ur * (er + pr)) - T(0.5) * a * (er - el);
+}
+
 // --------------------------------------------------------- cons -> prim
 // Sec. 3.1, Eq. 4: rho, v = M/rho, u_g = E - |M|^2/(2 rho). Floors act on the
 // primitives only. `hit` counts a floor firing, `bad` a non-finite state or
@@ -243,7 +261,7 @@ __device__ __forceinline__ void geo_init(Geo& g, const DevProblem& P, int m) {
 // Offset (in doubles, variable 0) of cell (i,j,k) given in this block's local
 // coordinates, of which at most one may lie outside the block by <= its size:
 // the ghost-zone rule of periodic / neighbour copies and outflow clamping.
-__device__ __forceinline__ int64_t ghost_off(const Geo& g, int i, int j, int k) {
+__device__ __forceinline__ int64_t ghost_local(const Geo& g, int i, int j, int k, int& mb_out) {
   int mb = g.m;
   if (i < 0) {
     if (g.nb[0] >= 0) { mb = g.nb[0]; i += g.bx; } else { i = 0; }
@@ -260,7 +278,21 @@ __device__ __forceinline__ int64_t ghost_off(const Geo& g, int i, int j, int k) 
   } else if (k >= g.bz) {
     if (g.nb[5] >= 0) { mb = g.nb[5]; k -= g.bz; } else { k = g.bz - 1; }
   }
-  return (int64_t)mb * g.bstride + ((int64_t)k * g.by + j) * g.bx + i;
+  mb_out = mb;
+  return ((int64_t)k * g.by + j) * g.bx + i;
+}
+
+__device__ __forceinline__ int64_t ghost_off(const Geo& g, int i, int j, int k) {
+  int mb;
+  const int64_t l = ghost_local(g, i, j, k, mb);
+  return (int64_t)mb * g.bstride + l;
+}
+
+// Cell index (block * cells per block + local) of the same ghost rule.
+__device__ __forceinline__ int64_t ghost_cell(const Geo& g, int i, int j, int k) {
+  int mb;
+  const int64_t l = ghost_local(g, i, j, k, mb);
+  return (int64_t)mb * g.vstride + l;
 }
 
 __device__ __forceinline__ void load5(const double* __restrict__ base, int64_t off, int64_t vs,
@@ -413,6 +445,11 @@ k_stage(const StageArgs a) {
     const bool count = (E.flags & 1) != 0;
 
     if (STAGE == 1 && loc == 0 && tid == 0) P.dtmin[E.parity ^ 1] = kInfBits;
+    const bool fofc = P.fofc && count;
+    if (fofc && loc == 0 && tid == 0) {  // fold the counter of two stages ago
+      *P.fofc_total = *P.fofc_total + P.fofc_cnt[(E.tag + 1) & 1];
+      P.fofc_cnt[(E.tag + 1) & 1] = 0ull;
+    }
 
     int hits = 0, bad = 0;
     double mydt = __longlong_as_double((long long)kInfBits);
@@ -632,6 +669,14 @@ k_stage(const StageArgs a) {
         }
 #pragma unroll
         for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(unew[v], Out + off + v * vs);
+        if (fofc) {  // first-order flux correction: flag a non-positive result
+          const double ke2 = (unew[1] * unew[1] + unew[2] * unew[2]) + unew[3] * unew[3];
+          const double pn = gm1 * (unew[4] - (0.5 * ke2) * rcp(unew[0]));
+          if (!(unew[0] > 0.0) || !(pn > 0.0)) {
+            P.tags[(int64_t)m * geo.vstride + k * pstride + (int64_t)gj * geo.bx + gi] = E.tag;
+            atomicAdd(P.fofc_cnt + (E.tag & 1), 1ull);
+          }
+        }
         if (STAGE == 2) mydt = fmin(mydt, cell_dt(fl, gamma, gm1, P.dx, unew));
       }
     }
@@ -658,6 +703,157 @@ k_stage(const StageArgs a) {
       }
     }
     __syncthreads();  // LDS reuse by the next tile of this workgroup
+  }
+}
+
+// ----------------------------------------------- first-order flux correction
+// Primitive of the cell at block-local (i,j,k) (at most one coordinate outside
+// the block), rounded to T exactly as the stage kernel rounds it.
+template <typename T>
+__device__ __forceinline__ void prim_at(const Geo& geo, const Floors& fl,
+                                        const double* __restrict__ S, int i, int j, int k, T w[5]) {
+  double u[5], wd[5];
+  int h = 0, b = 0;
+  load5c(S, ghost_off(geo, i, j, k), geo.vstride, u);
+  c2p(fl, u, wd, h, b);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) w[v] = (T)wd[v];
+}
+
+// The stage kernel's high-order flux and the first-order LLF flux through the
+// face between the cells (i,j,k) - e_d and (i,j,k), in conserved order.
+template <int RECON, typename T>
+__device__ void face_pair(const Geo& geo, const Floors& fl, const Gas<T>& gas,
+                          const double* __restrict__ S, int d, int i, int j, int k, T fho[5],
+                          T flf[5]) {
+  constexpr int NG = RECON == 0 ? 2 : 3;
+  T c[2 * NG][5];
+  const int di = d == 0, dj = d == 1, dk = d == 2;
+#pragma unroll
+  for (int o = 0; o < 2 * NG; ++o)
+    prim_at(geo, fl, S, i + (o - NG) * di, j + (o - NG) * dj, k + (o - NG) * dk, c[o]);
+  T wl[5], wr[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    if constexpr (RECON == 0) {
+      wl[v] = c[1][v] + T(0.5) * plm_slope(c[0][v], c[1][v], c[2][v]);
+      wr[v] = c[2][v] - T(0.5) * plm_slope(c[1][v], c[2][v], c[3][v]);
+    } else {
+      const T d1 = ppm_dm(c[0][v], c[1][v], c[2][v]), d2 = ppm_dm(c[1][v], c[2][v], c[3][v]);
+      const T d3 = ppm_dm(c[2][v], c[3][v], c[4][v]), d4 = ppm_dm(c[3][v], c[4][v], c[5][v]);
+      const T am = ppm_iface(c[1][v], c[2][v], d1, d2);
+      const T a0 = ppm_iface(c[2][v], c[3][v], d2, d3);
+      const T ap = ppm_iface(c[3][v], c[4][v], d3, d4);
+      T l1 = am, r1 = a0;
+      ppm_mono(c[2][v], l1, r1);
+      T l2 = a0, r2 = ap;
+      ppm_mono(c[3][v], l2, r2);
+      wl[v] = r1;
+      wr[v] = l2;
+    }
+  }
+  const T* a = c[NG - 1];
+  const T* b = c[NG];
+  // normal and tangential velocity slots per direction: x (1,2,3), y (2,3,1), z (3,1,2)
+  const int n = 1 + d, t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
+  T f[5], g[5];
+  hllc(gas, wl[0], wl[n], wl[t1], wl[t2], wl[4], wr[0], wr[n], wr[t1], wr[t2], wr[4], f);
+  llf(gas, a[0], a[n], a[t1], a[t2], a[4], b[0], b[n], b[t1], b[t2], b[4], g);
+  fho[0] = f[0]; fho[n] = f[1]; fho[t1] = f[2]; fho[t2] = f[3]; fho[4] = f[4];
+  flf[0] = g[0]; flf[n] = g[1]; flf[t1] = g[2]; flf[t2] = g[3]; flf[4] = g[4];
+}
+
+constexpr int kFixPlanes = 4;  // z-planes of one MeshBlock per workgroup pass
+
+// Replace, for every cell flagged in this stage, the fluxes on all its faces by
+// LLF fluxes of the first-order states: each cell that is flagged or has a
+// flagged face neighbour adds (F_LLF - F_HO) of its affected faces to its
+// stage result. Exits at once when nothing was flagged. Stage 2 also resets
+// the time-step slot for k_fofc_dt.
+template <int RECON, typename T>
+__global__ void __launch_bounds__(256) k_fofc_fix(const FixArgs a) {
+  const FixEntry E = a.e[blockIdx.y];
+  const DevProblem& P = *E.p;
+  if (P.fofc_cnt[E.tag & 1] == 0ull) return;
+  const int stage = a.stage;
+  if (stage == 2 && blockIdx.x == 0 && threadIdx.x == 0) P.dtmin[E.parity ^ 1] = kInfBits;
+  const double* __restrict__ S = stage == 1 ? P.U : P.V;
+  double* __restrict__ Out = stage == 1 ? P.V : P.U;
+  const double gamma = P.gamma, gm1 = gamma - 1.0;
+  const Gas<T> gas{T(gamma), T(gm1), T((gamma + 1.0) / (2.0 * gamma))};
+  const Floors fl{P.rho_floor, P.p_floor / gm1};
+  const double dt = P.cfl * __longlong_as_double((long long)P.dtmin[E.parity]);
+  const double cst = stage == 1 ? dt : 0.5 * dt;
+  const double id[3] = {1.0 / P.dx[0], 1.0 / P.dx[1], 1.0 / P.dx[2]};
+  const uint32_t tag = E.tag;
+  const int slabs = (P.bz + kFixPlanes - 1) / kFixPlanes;
+  for (int w = blockIdx.x; w < P.nblocks * slabs; w += gridDim.x) {
+    const int m = w / slabs, k0 = (w - m * slabs) * kFixPlanes;
+    Geo geo;
+    geo_init(geo, P, m);
+    const int k1 = min(k0 + kFixPlanes, geo.bz);
+    const int64_t plane = (int64_t)geo.bx * geo.by;
+    for (int64_t r = (int64_t)k0 * plane + threadIdx.x; r < (int64_t)k1 * plane; r += blockDim.x) {
+      const int k = (int)(r / plane);
+      const int rem = (int)(r - k * plane);
+      const int j = rem / geo.bx, i = rem - j * geo.bx;
+      const bool me = P.tags[(int64_t)m * geo.vstride + r] == tag;
+      bool nb[6];
+      nb[0] = P.tags[ghost_cell(geo, i - 1, j, k)] == tag;
+      nb[1] = P.tags[ghost_cell(geo, i + 1, j, k)] == tag;
+      nb[2] = P.tags[ghost_cell(geo, i, j - 1, k)] == tag;
+      nb[3] = P.tags[ghost_cell(geo, i, j + 1, k)] == tag;
+      nb[4] = P.tags[ghost_cell(geo, i, j, k - 1)] == tag;
+      nb[5] = P.tags[ghost_cell(geo, i, j, k + 1)] == tag;
+      if (!(me || nb[0] || nb[1] || nb[2] || nb[3] || nb[4] || nb[5])) continue;
+      double dL[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int d = 0; d < 3; ++d) {
+        for (int s = 0; s < 2; ++s) {
+          if (!me && !nb[2 * d + s]) continue;
+          T fho[5], flf[5];
+          face_pair<RECON, T>(geo, fl, gas, S, d, i + s * (d == 0), j + s * (d == 1), k + s * (d == 2),
+                              fho, flf);
+          // L = -(F_upper - F_lower)/dx: a lower face enters with +, an upper with -
+          const double sg = s ? -id[d] : id[d];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) dL[v] += sg * ((double)flf[v] - (double)fho[v]);
+        }
+      }
+      const int64_t off = (int64_t)m * geo.bstride + r;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Out[off + v * geo.vstride] += cst * dL[v];
+    }
+  }
+}
+
+// After a corrected stage 2: the time step from the corrected state.
+__global__ void __launch_bounds__(256) k_fofc_dt(const FixArgs a) {
+  const FixEntry E = a.e[blockIdx.y];
+  const DevProblem& P = *E.p;
+  if (P.fofc_cnt[E.tag & 1] == 0ull) return;
+  const double gamma = P.gamma, gm1 = gamma - 1.0;
+  const Floors fl{P.rho_floor, P.p_floor / gm1};
+  const int64_t ncell = (int64_t)P.nblocks * P.vstride;
+  double mydt = __longlong_as_double((long long)kInfBits);
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = c / P.vstride, rr = c - m * P.vstride;
+    double u[5];
+    load5c(P.U, m * P.bstride + rr, P.vstride, u);
+    mydt = fmin(mydt, cell_dt(fl, gamma, gm1, P.dx, u));
+  }
+  unsigned long long b = (unsigned long long)__double_as_longlong(mydt);
+  for (int s = kWave / 2; s > 0; s >>= 1) {
+    const unsigned long long o = __shfl_xor(b, s, kWave);
+    b = o < b ? o : b;
+  }
+  __shared__ unsigned long long red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long mn = red[0];
+    for (int w = 1; w < 4; ++w) mn = red[w] < mn ? red[w] : mn;
+    atomicMin(P.dtmin + (E.parity ^ 1), mn);
   }
 }
 
@@ -785,6 +981,17 @@ hipError_t launch_stage(int v, int recon, int prec, int stage, const StageArgs& 
   void* args[] = {(void*)&a};
   return hipLaunchKernel(sv.fn[recon][prec][stage - 1], dim3(grid), dim3(sv.tx * sv.ty), args, 0, s);
 }
+
+hipError_t launch_fofc(int recon, int prec, const FixArgs& a, int grid_x, hipStream_t s) {
+  static const void* fix[2][2] = {{(const void*)&k_fofc_fix<0, double>, (const void*)&k_fofc_fix<0, float>},
+                                  {(const void*)&k_fofc_fix<1, double>, (const void*)&k_fofc_fix<1, float>}};
+  void* args[] = {(void*)&a};
+  hipError_t e = hipLaunchKernel(fix[recon][prec], dim3(grid_x, a.nprob), dim3(256), args, 0, s);
+  if (e != hipSuccess || a.stage != 2) return e;
+  return hipLaunchKernel((const void*)&k_fofc_dt, dim3(grid_x, a.nprob), dim3(256), args, 0, s);
+}
+
+int fofc_grid(int nblocks, int bz) { return nblocks * ((bz + kFixPlanes - 1) / kFixPlanes); }
 
 hipError_t launch_reset(const DevProblem* p, int slot, int clear, hipStream_t s) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, p, slot, clear);

@@ -9,6 +9,8 @@ int stage_variant_waves(int v);
 const void* stage_kernel(int v, int recon, int prec, int stage);
 hipError_t launch_stage(int v, int recon, int prec, int stage, const StageArgs& a, int grid,
                         hipStream_t s);
+hipError_t launch_fofc(int recon, int prec, const FixArgs& a, int grid_x, hipStream_t s);
+int fofc_grid(int nblocks, int bz);
 hipError_t launch_reset(const DevProblem* p, int slot, int clear, hipStream_t s);
 hipError_t launch_dt(const DevProblem* p, int64_t ncell, int slot, int flags, hipStream_t s);
 hipError_t launch_scatter(const DevProblem* p, const double* src, double* dst, int64_t n,

@@ -38,6 +38,7 @@ class HyConfig(_c.Structure):
         ("cfl", _c.c_double),
         ("recon", _c.c_int32),
         ("precision", _c.c_int32),
+        ("fofc", _c.c_int32),
         ("rho_floor", _c.c_double),
         ("p_floor", _c.c_double),
     ]
@@ -55,7 +56,7 @@ SIGNATURES = {
     "hy_advance": ([_vp, _c.c_int32, _vp], _c.c_int),
     "hy_batch_advance": ([_c.POINTER(_vp), _i32p, _c.c_int32, _vp], _c.c_int),
     "hy_batch_advance_graph": ([_c.POINTER(_vp), _i32p, _c.c_int32, _vp], _c.c_int),
-    "hy_query": ([_vp, _dp, _dp, _i64p, _i64p], _c.c_int),
+    "hy_query": ([_vp, _dp, _dp, _i64p, _i64p, _i64p], _c.c_int),
     "hy_set_time": ([_vp, _c.c_double], _c.c_int),
     "hy_destroy": ([_vp], _c.c_int),
     "hy_last_error": ([], _c.c_char_p),
@@ -130,6 +131,7 @@ def make_config(pb) -> HyConfig:
     c.cfl = float(pb.cfl)
     c.recon = int(pb.recon)
     c.precision = int(pb.precision)
+    c.fofc = int(getattr(pb, "fofc", 0))
     c.rho_floor = float(pb.rho_floor)
     c.p_floor = float(pb.p_floor)
     return c
@@ -237,11 +239,13 @@ class Problem:
 
     def query(self, raise_on_state=True):
         t, dt = _c.c_double(), _c.c_double()
-        steps, fh = _c.c_int64(), _c.c_int64()
-        st = lib().hy_query(self.h, _c.byref(t), _c.byref(dt), _c.byref(steps), _c.byref(fh))
+        steps, fh, fc = _c.c_int64(), _c.c_int64(), _c.c_int64()
+        st = lib().hy_query(self.h, _c.byref(t), _c.byref(dt), _c.byref(steps), _c.byref(fh),
+                            _c.byref(fc))
         if st != HY_OK and (raise_on_state or st != HY_ERR_STATE):
             _check(st)
-        return dict(t=t.value, dt=dt.value, steps=steps.value, floor_hits=fh.value, status=st)
+        return dict(t=t.value, dt=dt.value, steps=steps.value, floor_hits=fh.value,
+                    fofc_cells=fc.value, status=st)
 
     def set_time(self, t):
         _check(lib().hy_set_time(self.h, float(t)))

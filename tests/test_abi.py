@@ -46,8 +46,19 @@ def test_workspace_bytes_and_validation_without_gpu():
     assert "ghost" in hy.last_error() or "divide" in hy.last_error()
 
 
-def test_struct_layout_matches_header():
+def test_struct_layout_matches_header(tmp_path):
+    # the ctypes mirror must match the C compiler's layout of hy_config
+    import subprocess
     from paper_2409_16053_amd import hy
-    assert ctypes.sizeof(hy.HyConfig) == 136
-    assert hy.HyConfig.gamma.offset == 96
-    assert hy.HyConfig.p_floor.offset == 128
+    fields = [f[0] for f in hy.HyConfig._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "hy.h"\nint main(void){\n'
+                   + 'printf("%zu\\n", sizeof(hy_config));\n'
+                   + "".join(f'printf("%zu\\n", offsetof(hy_config, {f}));\n' for f in fields)
+                   + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert vals[0] == ctypes.sizeof(hy.HyConfig)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(hy.HyConfig, f).offset == off, f

@@ -1,0 +1,96 @@
+"""GPU first-order flux correction (FOFC) against the CPU reference solver."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_16053_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hy():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_16053_amd import hy as _hy
+    _hy.lib()
+    return _hy
+
+
+def _run(hy, pb, steps, variant=None, kc=None):
+    g = hy.Problem(pb).set_state()
+    if variant is not None:
+        g.set_launch(variant, kc)
+    g.advance(steps)
+    U, q = g.get_state(), g.query()
+    g.close()
+    return U, q
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).sum() / np.abs(b).sum())
+
+
+def _pmin(U, g=5.0 / 3.0):
+    return ((g - 1) * (U[4] - 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0])).min()
+
+
+@pytest.mark.parametrize("recon", [P.PLM, P.PPM4])
+def test_fofc_hypersonic_turbulence_matches_reference(hy, recon):
+    pb = P.turbulence(N=32, seed=5, kmax=8, mach=20).with_(block=(16, 16, 16), recon=recon, fofc=1)
+    steps = 20
+    U, q = _run(hy, pb, steps)
+    ref = oracle.advance(pb, steps)
+    r = _rel(U, ref["U"])
+    print(f"[fofc recon {recon}] rel L1 {r:.3e}  cells {q['fofc_cells']}/{ref['fofc_cells']}  "
+          f"floors {q['floor_hits']}/{ref['floor_hits']}  dt {q['dt']:.15g}/{ref['dt']:.15g}", flush=True)
+    assert ref["fofc_cells"] > 0
+    assert q["fofc_cells"] == ref["fofc_cells"]
+    assert q["floor_hits"] == ref["floor_hits"]
+    assert r <= 1e-12
+    assert abs(q["dt"] / ref["dt"] - 1) <= 1e-11
+    assert _pmin(U) > 0
+
+
+def test_fofc_inactive_on_positive_flow(hy):
+    pb = P.kelvin_helmholtz(N=32, seed=6).with_(block=(16, 16, 16))
+    a, qa = _run(hy, pb, 8)
+    b, qb = _run(hy, pb.with_(fofc=1), 8)
+    assert qb["fofc_cells"] == 0 and np.array_equal(a, b) and qa["dt"] == qb["dt"]
+
+
+def test_fofc_tile_shapes_bitwise(hy):
+    pb = P.turbulence(N=32, seed=7, kmax=8, mach=15).with_(block=(32, 16, 16), fofc=1)
+    outs = [_run(hy, pb, 10, variant=v, kc=kc) for v, kc in ((0, 16), (3, 5), (5, 3))]
+    assert outs[0][1]["fofc_cells"] > 0
+    for U, q in outs[1:]:
+        assert np.array_equal(U, outs[0][0]) and q["fofc_cells"] == outs[0][1]["fofc_cells"]
+
+
+def test_fofc_batch_equals_alone(hy):
+    pbs = [P.turbulence(N=32, seed=8, kmax=8, mach=20).with_(block=(16, 16, 16), fofc=1),
+           P.sedov(N=32, seed=9).with_(block=(16, 16, 16)),
+           P.turbulence(N=24, seed=10, kmax=6, mach=15).with_(block=(24, 24, 24), fofc=1)]
+    steps = [9, 6, 7]
+    alone = [_run(hy, pb, n) for pb, n in zip(pbs, steps)]
+    gs = [hy.Problem(pb).set_state() for pb in pbs]
+    hy.batch_advance(gs, steps)
+    for g, (U, q) in zip(gs, alone):
+        Ub, qb = g.get_state(), g.query()
+        assert np.array_equal(Ub, U) and qb["fofc_cells"] == q["fofc_cells"] and qb["dt"] == q["dt"]
+        g.close()
+
+
+def test_fofc_mixed_precision_positive_and_conservative(hy):
+    pb = P.turbulence(N=32, seed=5, kmax=8, mach=20).with_(block=(16, 16, 16), fofc=1,
+                                                           precision=P.MIXED)
+    U, q = _run(hy, pb, 20)
+    ref = oracle.advance(pb.with_(precision=P.FP64), 20)
+    print(f"[fofc mixed] cells {q['fofc_cells']} (FP64 reference {ref['fofc_cells']}), "
+          f"rel L1 vs FP64 reference {_rel(U, ref['U']):.3e}", flush=True)
+    assert q["fofc_cells"] > 0 and _pmin(U) > 0
+    eps = np.finfo(np.float64).eps
+    for v in range(5):
+        scale = np.abs(pb.U[v]).sum() + np.abs(U[v]).sum()
+        assert abs(U[v].sum() - pb.U[v].sum()) <= 4 * eps * np.sqrt(pb.cells * 40) * scale

@@ -1,0 +1,80 @@
+"""Parity at the full benchmark sizes, in the launch shape the benchmark
+times (chosen by the same whole-step autotuning on a scratch copy).
+
+* 256^3 turbulence in 64 MeshBlocks of 64^3, PLM, 20 steps: the whole state
+  against the CPU reference solver, FP64 (rel L1 <= 1e-12) and mixed
+  precision (<= 1e-5).
+* 512^3 Kelvin-Helmholtz in 64 MeshBlocks of 128^3, PPM4: the whole state
+  after 2 steps against the reference solver (10 steps of the reference at
+  this size take minutes of host time), and over the full 10 steps the
+  properties that hold at any size: conservation to roundoff on the periodic
+  grid, no floor firings, and FP64 vs mixed agreement within the mixed gate.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_16053_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hy():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_16053_amd import hy as _hy
+    _hy.lib()
+    return _hy
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).sum() / np.abs(b).sum())
+
+
+def _run_tuned(hy, pb, steps):
+    g = hy.Problem(pb).set_state()
+    v, kc, _ = g.autotune_steps(2)
+    g.advance(steps)
+    U, q = g.get_state(), g.query()
+    g.close()
+    return U, q, (v, kc)
+
+
+def test_turbulence_256_full_size(hy):
+    pb, steps = P.workload_turbulence_256()
+    print(f"[turb256] reference solver, {steps} steps", flush=True)
+    ref = oracle.advance(pb, steps)
+    for prec, gate in ((P.FP64, 1e-12), (P.MIXED, 1e-5)):
+        U, q, shape = _run_tuned(hy, pb.with_(precision=prec), steps)
+        r = _rel(U, ref["U"])
+        print(f"[turb256 prec {prec}] launch {shape} rel L1 {r:.3e} "
+              f"dt {q['dt']:.15g}/{ref['dt']:.15g}", flush=True)
+        assert r <= gate
+        assert q["steps"] == steps and q["floor_hits"] == 0
+        if prec == P.FP64:
+            assert abs(q["dt"] / ref["dt"] - 1) <= 1e-11
+        del U
+
+
+def test_kh_512_full_size(hy):
+    pb, steps = P.workload_kh_512()
+    print("[kh512] reference solver, 2 steps", flush=True)
+    ref = oracle.advance(pb, 2)
+    U2, q2, shape = _run_tuned(hy, pb, 2)
+    r = _rel(U2, ref["U"])
+    print(f"[kh512 2 steps] launch {shape} rel L1 {r:.3e}", flush=True)
+    assert r <= 1e-12
+    del ref, U2
+    U, q, _ = _run_tuned(hy, pb, steps)
+    assert q["floor_hits"] == 0 and np.isfinite(U).all()
+    eps = np.finfo(np.float64).eps
+    bound = 4 * eps * np.sqrt(pb.cells * 2 * steps)
+    for v in range(5):
+        scale = np.abs(pb.U[v]).sum() + np.abs(U[v]).sum()
+        assert abs(U[v].sum() - pb.U[v].sum()) <= bound * scale, v
+    Um, qm, _ = _run_tuned(hy, pb.with_(precision=P.MIXED), steps)
+    r = _rel(Um, U)
+    print(f"[kh512 {steps} steps] mixed vs FP64 rel L1 {r:.3e}", flush=True)
+    assert r <= 1e-5
