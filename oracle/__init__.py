@@ -37,6 +37,7 @@ class Params(ctypes.Structure):
         ("bc", (ctypes.c_int32 * 2) * 3),
         ("recon", ctypes.c_int32),
         ("fofc", ctypes.c_int32),
+        ("rk", ctypes.c_int32),
         ("dx", ctypes.c_double * 3),
         ("gamma", ctypes.c_double),
         ("cfl", ctypes.c_double),
@@ -63,6 +64,8 @@ def _bind(L):
     L.or_plm_cell.restype = None
     L.or_ppm4_cell.argtypes = [dp, dp, dp]
     L.or_ppm4_cell.restype = None
+    L.or_wenoz_cell.argtypes = [dp, dp, dp]
+    L.or_wenoz_cell.restype = None
     L.or_hllc.argtypes = [ctypes.c_double, dp, dp, dp]
     L.or_hllc.restype = None
     L.or_llf.argtypes = [ctypes.c_double, dp, dp, dp]
@@ -102,6 +105,7 @@ def params(pb) -> Params:
         P.dx[d] = float(pb.dx[d])
     P.recon = int(pb.recon)
     P.fofc = int(getattr(pb, "fofc", 0))
+    P.rk = int(getattr(pb, "rk", 2))
     P.gamma = float(pb.gamma)
     P.cfl = float(pb.cfl)
     P.rho_floor = float(pb.rho_floor)
@@ -190,6 +194,12 @@ class Oracle:
         self._L.or_ppm4_cell(_dp(w), ctypes.byref(l), ctypes.byref(r))
         return l.value, r.value
 
+    def wenoz_cell(self, w5):
+        w = np.ascontiguousarray(w5, dtype=np.float64)
+        l, r = ctypes.c_double(), ctypes.c_double()
+        self._L.or_wenoz_cell(_dp(w), ctypes.byref(l), ctypes.byref(r))
+        return l.value, r.value
+
     def llf(self, gamma, wl, wr):
         """LLF flux for primitive states [rho, u_n, u_t1, u_t2, p]."""
         a = np.ascontiguousarray(wl, dtype=np.float64)
@@ -251,6 +261,10 @@ def plm_cell(wm, w0, wp):
 
 def ppm4_cell(w5):
     return _inst().ppm4_cell(w5)
+
+
+def wenoz_cell(w5):
+    return _inst().wenoz_cell(w5)
 
 
 def hllc(gamma, wl, wr):

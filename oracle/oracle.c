@@ -11,9 +11,10 @@
  * advance"):
  *   ghost-zone fill (Sec. 2, boundary conditions)
  *   -> conserved to primitive, W = [rho, v, u_g], p = (gamma-1) u_g (Sec. 3.1, Eq. 4)
- *   -> reconstruction on primitives, PLM or PPM4 (Sec. 3)
+ *   -> reconstruction on primitives, PLM, PPM4 or WENO-Z (Sec. 3)
  *   -> HLLC Riemann fluxes in x, y and z (Sec. 3; Toro's textbook, Ch. 10)
- *   -> flux divergence and a low-storage SSP-RK2 stage (Sec. 3, method of lines)
+ *   -> flux divergence and a low-storage SSP-RK stage (Sec. 3, method of lines;
+ *      one, two or three stages)
  *   -> CFL time step, Eq. 3: CFL times the minimum over all cells and all
  *      dimensions of dx_d / lambda_max,d.
  * It works on the whole mesh with no MeshBlock decomposition: splitting the
@@ -22,8 +23,11 @@
  * Readings where the paper is silent (each is listed with its reason in the
  * design notes): PLM uses the van Leer harmonic-mean limiter; PPM4 is
  * Colella & Woodward (1984) Eqs. 1.6-1.10 without steepening or flattening;
+ * WENO-Z uses the Jiang-Shu smoothness indicators with the squared WENO-Z
+ * weights of Borges et al. (2008);
  * the reconstructed energy variable is u_g; HLLC is Toro-Spruce-Speares with
- * PVRS pressure-based wave speeds; RK2 is SSPRK(2,2) in low-storage form;
+ * PVRS pressure-based wave speeds; RK2 is SSPRK(2,2) and RK3 SSPRK(3,3) of
+ * Shu & Osher, both in two-register low-storage form;
  * lambda_d = |v_d| + c_s; floors act on W only and never change U; outflow is
  * a zero-gradient copy of U.
  *
@@ -40,15 +44,16 @@
 #endif
 
 enum { OR_PERIODIC = 0, OR_OUTFLOW = 1 };
-enum { OR_PLM = 0, OR_PPM4 = 1 };
+enum { OR_PLM = 0, OR_PPM4 = 1, OR_WENOZ = 2 };
 enum { OR_OK = 0, OR_ERR_ARG = 1, OR_ERR_NOMEM = 2, OR_ERR_STATE = 4 };
 
 /* Problem description passed from Python (ctypes mirror in oracle/__init__.py). */
 typedef struct {
   int32_t n[3];      /* interior cells nx, ny, nz                      */
   int32_t bc[3][2];  /* per axis (lower, upper): OR_PERIODIC/OR_OUTFLOW */
-  int32_t recon;     /* OR_PLM (2 ghosts) or OR_PPM4 (3 ghosts)        */
+  int32_t recon;     /* OR_PLM (2 ghosts), OR_PPM4 or OR_WENOZ (3)     */
   int32_t fofc;      /* 1: first-order flux correction in every stage  */
+  int32_t rk;        /* stages of the SSP-RK integrator: 1, 2 or 3     */
   double dx[3];      /* cell widths                                    */
   double gamma;      /* ratio of specific heats, > 1                   */
   double cfl;        /* Courant number                                 */
@@ -76,7 +81,7 @@ static size_t at(const grid* G, int v, int i, int j, int k) {
          ((size_t)(k + G->g) * G->s[1] + (size_t)(j + G->g)) * G->s[0] + (size_t)(i + G->g);
 }
 
-int or_nghost(int recon) { return recon == OR_PPM4 ? 3 : 2; }
+int or_nghost(int recon) { return recon == OR_PLM ? 2 : 3; }
 
 void or_set_threads(int n) {
 #ifdef _OPENMP
@@ -215,6 +220,55 @@ void or_ppm4_cell(const double w[5], double* left, double* right) {
   }
   *left = aL;
   *right = aR;
+}
+
+/* ------------------------------------------------------------------------
+ * WENO-Z (Sec. 3 names the improved WENO-Z of Acker et al. 2016 and defers
+ * its details). Fifth-order weighted combination of the three third-order
+ * candidate values of the face, with the Jiang-Shu smoothness indicators
+ * beta_k, the global indicator tau5 = |beta_0 - beta_2| and the WENO-Z
+ * weights alpha_k = d_k (1 + (tau5 / (beta_k + eps))^2), linear weights
+ * d = (1/10, 6/10, 3/10) (Borges et al. 2008). The ratio is capped at 1e15,
+ * which keeps the weights finite in single precision and changes them only
+ * where one candidate already has weight 1 to within 1e-30.
+ * ---------------------------------------------------------------------- */
+#define OR_WENO_EPS 1e-36
+#define OR_WENO_CAP 1e15
+
+/* value at the right face of the middle cell of w[0..4] (cells c-2..c+2) */
+static double weno_right(const double w[5]) {
+  const double b0 = 13.0 / 12.0 * (w[0] - 2.0 * w[1] + w[2]) * (w[0] - 2.0 * w[1] + w[2]) +
+                    0.25 * (w[0] - 4.0 * w[1] + 3.0 * w[2]) * (w[0] - 4.0 * w[1] + 3.0 * w[2]);
+  const double b1 = 13.0 / 12.0 * (w[1] - 2.0 * w[2] + w[3]) * (w[1] - 2.0 * w[2] + w[3]) +
+                    0.25 * (w[1] - w[3]) * (w[1] - w[3]);
+  const double b2 = 13.0 / 12.0 * (w[2] - 2.0 * w[3] + w[4]) * (w[2] - 2.0 * w[3] + w[4]) +
+                    0.25 * (3.0 * w[2] - 4.0 * w[3] + w[4]) * (3.0 * w[2] - 4.0 * w[3] + w[4]);
+  const double beta[3] = {b0, b1, b2};
+  const double d[3] = {0.1, 0.6, 0.3};
+  /* candidates minus the cell value: (2 w0 - 7 w1 + 11 w2)/6, (-w1 + 5 w2 + 2 w3)/6
+   * and (2 w2 + 5 w3 - w4)/6, written in differences so that a constant
+   * state is reproduced exactly */
+  const double dq[3] = {(2.0 * (w[0] - w[1]) - 5.0 * (w[1] - w[2])) / 6.0,
+                        (2.0 * (w[3] - w[2]) - (w[1] - w[2])) / 6.0,
+                        (4.0 * (w[3] - w[2]) - (w[4] - w[3])) / 6.0};
+  const double tau = fabs(b0 - b2);
+  double num = 0.0, den = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    double r = tau / (beta[k] + OR_WENO_EPS);
+    if (r > OR_WENO_CAP) r = OR_WENO_CAP;
+    const double a = d[k] * (1.0 + r * r);
+    num += a * dq[k];
+    den += a;
+  }
+  return w[2] + num / den;
+}
+
+/* WENO-Z face values of cell c from w[0..4] = cells c-2..c+2; the left face
+ * is the right-face formula applied to the mirrored stencil. */
+void or_wenoz_cell(const double w[5], double* left, double* right) {
+  const double m[5] = {w[4], w[3], w[2], w[1], w[0]};
+  *right = weno_right(w);
+  *left = weno_right(m);
 }
 
 /* ------------------------------------------------------------------------
@@ -359,8 +413,13 @@ static void face_states(const or_params* p, const work* w, int d, int i, int j, 
     } else {
       for (int o = -3; o <= 2; ++o) s[o + 3] = w->W[at(G, v, i + o * di, j + o * dj, k + o * dk)];
       double l0, r0, l1, r1;
-      or_ppm4_cell(&s[0], &l0, &r0); /* cell c-1: cells c-3..c+1 */
-      or_ppm4_cell(&s[1], &l1, &r1); /* cell c:   cells c-2..c+2 */
+      if (p->recon == OR_PPM4) {
+        or_ppm4_cell(&s[0], &l0, &r0); /* cell c-1: cells c-3..c+1 */
+        or_ppm4_cell(&s[1], &l1, &r1); /* cell c:   cells c-2..c+2 */
+      } else {
+        or_wenoz_cell(&s[0], &l0, &r0);
+        or_wenoz_cell(&s[1], &l1, &r1);
+      }
       wl[v] = r0;
       wr[v] = l1;
     }
@@ -493,24 +552,47 @@ double or_new_dt(const or_params* p, const double* U) {
  * on all faces of that cell are replaced by LLF fluxes of the first-order
  * (piecewise-constant) states -- the primitives of the two cells sharing the
  * face -- and the stage update is recomputed with the corrected fluxes.
- * Stage 1: Uout = Ust + h L.  Stage 2: Uout = U0/2 + Ust/2 + h L/2.
+ * A stage forms Uout = a U0 + b Ust + c h L(Ust) from the step-start state
+ * U0 and the previous stage's state Ust (coefficients in rk_stage below).
  * Returns the number of corrected cells.
  * ---------------------------------------------------------------------- */
-static void stage_formula(const or_params* p, const work* w, int stage, const double* U0,
+typedef struct {
+  double a, b, c;
+} rk_coef;
+
+/* Stage coefficients of the two-register low-storage SSP-RK integrators
+ * (Sec. 3 cites Ketcheson 2010 for the family):
+ *   RK1 forward Euler:            (0, 1, 1)
+ *   RK2 SSPRK(2,2):               (0, 1, 1), (1/2, 1/2, 1/2)
+ *   RK3 SSPRK(3,3) (Shu & Osher): (0, 1, 1), (3/4, 1/4, 1/4), (1/3, 2/3, 2/3) */
+static rk_coef rk_stage(int rk, int stage) {
+  rk_coef k = {0.0, 1.0, 1.0};
+  if (stage == 1) return k;
+  if (rk == 2) {
+    k.a = 0.5; k.b = 0.5; k.c = 0.5;
+  } else if (stage == 2) {
+    k.a = 0.75; k.b = 0.25; k.c = 0.25;
+  } else {
+    k.a = 1.0 / 3.0; k.b = 2.0 / 3.0; k.c = 2.0 / 3.0;
+  }
+  return k;
+}
+
+static void stage_formula(const or_params* p, const work* w, rk_coef k, const double* U0,
                           const double* Ust, double h, double* Uout) {
   const size_t nt = 5 * ncell(p);
-  if (stage == 1) {
+  if (k.a == 0.0) {  /* first stage: Ust + h L */
 #pragma omp parallel for schedule(static)
     for (size_t c = 0; c < nt; ++c) Uout[c] = Ust[c] + h * w->L[c];
   } else {
 #pragma omp parallel for schedule(static)
-    for (size_t c = 0; c < nt; ++c) Uout[c] = 0.5 * U0[c] + 0.5 * Ust[c] + 0.5 * h * w->L[c];
+    for (size_t c = 0; c < nt; ++c) Uout[c] = k.a * U0[c] + k.b * Ust[c] + k.c * h * w->L[c];
   }
 }
 
-static long long stage_apply(const or_params* p, work* w, int stage, const double* U0,
+static long long stage_apply(const or_params* p, work* w, rk_coef k, const double* U0,
                              const double* Ust, double h, double* Uout) {
-  stage_formula(p, w, stage, U0, Ust, h, Uout);
+  stage_formula(p, w, k, U0, Ust, h, Uout);
   if (!p->fofc) return 0;
   const int nx = p->n[0], ny = p->n[1], nz = p->n[2];
   const size_t nc = ncell(p);
@@ -553,16 +635,20 @@ static long long stage_apply(const or_params* p, work* w, int stage, const doubl
       }
   if (flagged) {
     flux_divergence(p, w);
-    stage_formula(p, w, stage, U0, Ust, h, Uout);
+    stage_formula(p, w, k, U0, Ust, h, Uout);
   }
   return flagged;
 }
 
 /* ------------------------------------------------------------------------
- * Advance U[5][nz][ny][nx] by nsteps SSP-RK2 steps (Sec. 3, method of lines,
- * low-storage SSP-RK of Ketcheson 2010, two stages):
+ * Advance U[5][nz][ny][nx] by nsteps SSP-RK steps (Sec. 3, method of lines,
+ * low-storage SSP-RK of the Ketcheson 2010 family; p->rk stages). With RK2:
  *   U1      = Un + dt L(Un)
  *   U(n+1)  = Un/2 + U1/2 + dt L(U1)/2
+ * and with RK3:
+ *   U1      = Un + dt L(Un)
+ *   U2      = 3/4 Un + 1/4 U1 + 1/4 dt L(U1)
+ *   U(n+1)  = 1/3 Un + 2/3 U2 + 2/3 dt L(U2)
  * (each stage followed by FOFC when enabled), then dt for the next step from
  * U(n+1). *dt carries the step size in and the next one out; *t,
  * *floor_hits and *fofc_cells accumulate (either counter may be NULL).
@@ -576,6 +662,7 @@ int or_advance(const or_params* p, double* U, int nsteps, double* t, double* dt,
     if (p->n[d] < 1) return OR_ERR_ARG;
     if ((p->bc[d][0] == OR_PERIODIC) != (p->bc[d][1] == OR_PERIODIC)) return OR_ERR_ARG;
   }
+  if (p->rk < 1 || p->rk > 3 || p->recon < OR_PLM || p->recon > OR_WENOZ) return OR_ERR_ARG;
   work w;
   if (work_alloc(&w, p) != OR_OK) { work_free(&w); return OR_ERR_NOMEM; }
   const size_t nt = 5 * ncell(p);
@@ -586,14 +673,16 @@ int or_advance(const or_params* p, double* U, int nsteps, double* t, double* dt,
   long long hits = 0, fofc = 0;
   for (int s = 0; s < nsteps; ++s) {
     const double h = *dt;
-    int bad = 0;
-    hits += divergence(p, &w, U, &bad);
-    if (bad) status = OR_ERR_STATE;
-    fofc += stage_apply(p, &w, 1, U, U, h, U1);
-    hits += divergence(p, &w, U1, &bad);
-    if (bad) status = OR_ERR_STATE;
-    fofc += stage_apply(p, &w, 2, U, U1, h, U2);
-    memcpy(U, U2, nt * sizeof(double));
+    const double* st = U;  /* state the stage differentiates */
+    for (int stage = 1; stage <= p->rk; ++stage) {
+      int bad = 0;
+      hits += divergence(p, &w, st, &bad);
+      if (bad) status = OR_ERR_STATE;
+      double* out = (stage & 1) ? U1 : U2;  /* never the stage's own input */
+      fofc += stage_apply(p, &w, rk_stage(p->rk, stage), U, st, h, out);
+      st = out;
+    }
+    memcpy(U, st, nt * sizeof(double));
     *t += h;
     *dt = or_new_dt(p, U);
   }

@@ -27,12 +27,14 @@ PERIODIC = 0
 OUTFLOW = 1
 PLM = 0
 PPM4 = 1
+WENOZ = 2
 FP64 = 0
 MIXED = 1
 
 # Ghost depth each reconstruction needs: PLM reads c-1..c+1 of a cell, so a face
-# needs two cells on each side; PPM4 (Colella & Woodward 1984) needs three.
-NGHOST = {PLM: 2, PPM4: 3}
+# needs two cells on each side; PPM4 (Colella & Woodward 1984) and WENO-Z
+# (c-2..c+2 of a cell) need three.
+NGHOST = {PLM: 2, PPM4: 3, WENOZ: 3}
 
 
 @dataclass
@@ -52,6 +54,7 @@ class Problem:
     rho_floor: float = 1e-10
     p_floor: float = 1e-13
     fofc: int = 0                 # first-order flux correction (Sec. 3) on/off
+    rk: int = 2                   # SSP-RK stages (Sec. 3): 1, 2 or 3
     name: str = ""
     meta: dict = field(default_factory=dict)
 
@@ -355,6 +358,75 @@ def sod(N=128, axis=None, seed=4, ntrans=None, gamma=5.0 / 3.0, x0=0.5, **kw):
     bcs = ((OUTFLOW, OUTFLOW),) * 3
     return Problem(n=tuple(n), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=bcs, U=U,
                    gamma=gamma, name="sod", meta=dict(axis=axis, x0=x0), **kw)
+
+
+def entropy_wave(N=32, amp=0.2, v0=1.0, p0=1.0, rho0=1.0, t=0.0, axis=0, ntrans=1,
+                 gamma=5.0 / 3.0, **kw):
+    """Cell-averaged entropy (density) wave advected at ``v0`` along ``axis``
+    of the periodic unit domain, with uniform pressure and velocity.
+
+    The paper's linear-wave tests cover entropy waves beside sound waves
+    (Sec. 3.1). With uniform p and v the Euler equations reduce exactly to
+    advection of rho, so rho(x, t) = rho0 + amp sin(2 pi (x - v0 t)) for any
+    amplitude. Momentum and energy are linear in rho at fixed (v, p), so each
+    cell holds the exact average: the centre value times sinc(pi dx).
+    ``t`` > 0 gives the exact solution at that time.
+    """
+    n = [ntrans, ntrans, ntrans]
+    n[axis] = N
+    nx, ny, nz = n
+    xc = _centres(N, 0.0, 1.0)
+    h = 1.0 / N
+    a = np.pi * h
+    rho1 = rho0 + amp * np.sin(2.0 * np.pi * (xc - v0 * t)) * (np.sin(a) / a)
+    view = [1, 1, 1]
+    view[2 - axis] = N
+    rho = np.broadcast_to(rho1.reshape(view), (nz, ny, nx))
+    v = [0.0, 0.0, 0.0]
+    v[axis] = v0
+    U = np.empty((5, nz, ny, nx), dtype=np.float64)
+    U[0] = rho
+    for d in range(3):
+        U[1 + d] = rho * v[d]
+    U[4] = p0 / (gamma - 1.0) + 0.5 * rho * (v0 * v0)
+    bcs = ((PERIODIC, PERIODIC),) * 3
+    return Problem(n=tuple(n), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=bcs, U=U,
+                   gamma=gamma, name="entropy_wave",
+                   meta=dict(period=1.0 / abs(v0), axis=axis, amp=amp), **kw)
+
+
+def shu_osher(N=200, axis=0, ntrans=1, gamma=1.4, **kw):
+    """Shu & Osher's shock-entropy interaction (the paper's Fig. 2 right panel
+    shows it): on [-5, 5], a Mach-3 shock at x = -4 moves right into
+    rho = 1 + 0.2 sin(5x), p = 1, v = 0; the post-shock state is
+    (rho, v, p) = (3.857143, 2.629369, 10.33333). Cell-centre point values,
+    outflow boundaries, gamma = 1.4; the customary end time is 1.8.
+    """
+    n = [ntrans, ntrans, ntrans]
+    n[axis] = N
+    nx, ny, nz = n
+    xc = _centres(N, -5.0, 5.0)
+    post = xc < -4.0
+    rho1 = np.where(post, 3.857143, 1.0 + 0.2 * np.sin(5.0 * xc))
+    v1 = np.where(post, 2.629369, 0.0)
+    p1 = np.where(post, 10.33333, 1.0)
+    view = [1, 1, 1]
+    view[2 - axis] = N
+    shape = (nz, ny, nx)
+    rho = np.broadcast_to(rho1.reshape(view), shape)
+    vel = np.broadcast_to(v1.reshape(view), shape)
+    p = np.broadcast_to(p1.reshape(view), shape)
+    v = [0.0, 0.0, 0.0]
+    v[axis] = vel
+    U = conserved(rho, v[0], v[1], v[2], p, gamma)
+    lo, hi = [0.0, 0.0, 0.0], [1.0, 1.0, 1.0]
+    lo[axis], hi[axis] = -5.0, 5.0
+    for d in range(3):
+        if d != axis:
+            hi[d] = 10.0 / N
+    bcs = ((OUTFLOW, OUTFLOW),) * 3
+    return Problem(n=tuple(n), lo=tuple(lo), hi=tuple(hi), bc=bcs, U=U, gamma=gamma,
+                   name="shu_osher", meta=dict(axis=axis, t_end=1.8), **kw)
 
 
 # --------------------------------------------------------------------------

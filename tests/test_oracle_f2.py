@@ -1,0 +1,229 @@
+"""Pins of the higher-order options of the CPU reference solver: WENO-Z
+reconstruction and the one- and three-stage SSP-RK integrators (Sec. 3).
+
+* WENO-Z face values are exact for cell averages of quadratics (each
+  third-order candidate is), converge at fifth order on smooth data, and take
+  the smooth side of a jump (the ENO property).
+* Entropy waves (Sec. 3.1 tests both entropy and sound waves) are exact
+  solutions of the Euler equations at any amplitude, so they measure the
+  discretisation error alone: WENO-Z + RK3 converges at the high order the
+  paper reports for its extremum-preserving schemes (at least fourth), PPM4
+  at second order; at fixed resolution the error falls with the time step at
+  third order for RK3, second for RK2 and first for RK1.
+* Shu & Osher's shock-entropy interaction (the paper's Fig. 2): at 200 cells
+  WENO-Z + RK3 resolves the post-shock entropy waves better than PLM + RK2.
+"""
+import numpy as np
+import pytest
+
+from paper_2409_16053_amd import problems as P
+
+
+def _avg_poly(c, a, b):
+    """Exact average over [a, b] of sum_k c[k] x^k."""
+    F = lambda x: sum(ck * x ** (k + 1) / (k + 1) for k, ck in enumerate(c))
+    return (F(b) - F(a)) / (b - a)
+
+
+# ------------------------------------------------------------ WENO-Z units
+def test_wenoz_exact_for_quadratics(oracle_lib):
+    rng = np.random.default_rng(21)
+    for _ in range(50):
+        c = rng.normal(size=3)
+        h = 10.0 ** rng.uniform(-2, 0)
+        x0 = rng.uniform(-1, 1)
+        w = [_avg_poly(c, x0 + (m - 0.5) * h, x0 + (m + 0.5) * h) for m in range(-2, 3)]
+        left, right = oracle_lib.wenoz_cell(w)
+        p = lambda x: c[0] + c[1] * x + c[2] * x * x
+        scale = max(abs(v) for v in w) + 1.0
+        assert abs(right - p(x0 + 0.5 * h)) <= 1e-13 * scale
+        assert abs(left - p(x0 - 0.5 * h)) <= 1e-13 * scale
+
+
+def test_wenoz_matches_its_definition(oracle_lib):
+    # Rebuild the WENO-Z value from the definitions rather than the closed
+    # forms: each candidate is the quadratic whose averages over its three
+    # cells match the data (evaluated at the face); each smoothness indicator
+    # is the Jiang-Shu integral over the middle cell of h (p')^2 + h^3 (p'')^2.
+    from numpy.polynomial import Polynomial as Poly
+    rng = np.random.default_rng(23)
+    for trial in range(40):
+        w = rng.normal(size=5) * 10.0 ** rng.uniform(-3, 1)
+        q, beta = [], []
+        for k in range(3):
+            cells = np.arange(k - 2, k + 1)  # centres relative to the middle cell
+            # average of x^m over [c - 1/2, c + 1/2]
+            A = np.array([[((c + 0.5) ** (m + 1) - (c - 0.5) ** (m + 1)) / (m + 1)
+                           for m in range(3)] for c in cells])
+            p = Poly(np.linalg.solve(A, w[k:k + 3]))
+            q.append(p(0.5))
+            d1, d2 = p.deriv(1), p.deriv(2)
+            b = (d1 * d1).integ()(0.5) - (d1 * d1).integ()(-0.5)
+            b += (d2 * d2).integ()(0.5) - (d2 * d2).integ()(-0.5)
+            beta.append(b)
+        tau = abs(beta[0] - beta[2])
+        a = np.array([dk * (1.0 + min(tau / (bk + 1e-36), 1e15) ** 2)
+                      for dk, bk in zip((0.1, 0.6, 0.3), beta)])
+        expect = float(a @ np.array(q) / a.sum())
+        _, right = oracle_lib.wenoz_cell(w)
+        assert abs(right - expect) <= 1e-11 * np.abs(w).max(), (trial, right, expect)
+
+
+def test_wenoz_fifth_order_on_smooth_data(oracle_lib):
+    # f(x) = exp(sin x) near x = 0.3 (no critical point); cell averages from
+    # a fine midpoint sum of the exact antiderivative-free integrand
+    def avg(a, b, m=4001):
+        x = np.linspace(a, b, m)
+        return np.trapezoid(np.exp(np.sin(x)), x) / (b - a)
+
+    errs = []
+    for h in (0.1, 0.05, 0.025):
+        x0 = 0.3 - 0.5 * h  # the right face of the middle cell sits at 0.3
+        w = [avg(x0 + (m - 0.5) * h, x0 + (m + 0.5) * h) for m in range(-2, 3)]
+        _, right = oracle_lib.wenoz_cell(w)
+        errs.append(abs(right - np.exp(np.sin(0.3))))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 4.5), (errs, rates)
+
+
+def test_wenoz_takes_the_smooth_side_of_a_jump(oracle_lib):
+    for lo_, hi_ in ((0.0, 1.0), (2.0, -3.0), (0.125, 1.0)):
+        left, right = oracle_lib.wenoz_cell([lo_, lo_, lo_, hi_, hi_])
+        assert abs(right - lo_) <= 1e-12 * (abs(lo_) + abs(hi_))
+        assert abs(left - lo_) <= 1e-12 * (abs(lo_) + abs(hi_))
+        left, right = oracle_lib.wenoz_cell([lo_, lo_, hi_, hi_, hi_])
+        assert abs(right - hi_) <= 1e-12 * (abs(lo_) + abs(hi_))
+        assert abs(left - hi_) <= 1e-12 * (abs(lo_) + abs(hi_))
+
+
+def test_wenoz_mirror_and_constant(oracle_lib):
+    rng = np.random.default_rng(22)
+    for _ in range(20):
+        w = rng.normal(size=5)
+        l1, r1 = oracle_lib.wenoz_cell(w)
+        l2, r2 = oracle_lib.wenoz_cell(w[::-1])
+        assert l1 == r2 and r1 == l2
+        l3, r3 = oracle_lib.wenoz_cell(-w)
+        assert l3 == -l1 and r3 == -r1
+    assert oracle_lib.wenoz_cell([0.7] * 5) == (0.7, 0.7)
+
+
+# ------------------------------------------------------------ entropy waves
+def _run_to(oracle_lib, pb, t_end, max_steps=50000):
+    U, t, dt = pb.U, 0.0, oracle_lib.new_dt(pb, pb.U)
+    for _ in range(max_steps):
+        if t >= t_end - 1e-14:
+            return U
+        assert np.isfinite(dt) and dt > 0.0, dt
+        h = min(dt, t_end - t)
+        r = oracle_lib.advance(pb, 1, U=U, t=t, dt=h)
+        assert r["status"] == 0
+        U, t, dt = r["U"], r["t"], r["dt"]
+    raise AssertionError("time step collapsed")
+
+
+def _entropy_error(oracle_lib, N, recon, rk, cfl, axis=0, amp=0.2):
+    pb = P.entropy_wave(N=N, amp=amp, axis=axis).with_(recon=recon, rk=rk, cfl=cfl)
+    U = _run_to(oracle_lib, pb, 1.0)
+    ex = P.entropy_wave(N=N, amp=amp, axis=axis, t=1.0).U
+    return float(np.abs(U[0] - ex[0]).mean() / amp)
+
+
+def _rates(errs):
+    return np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_entropy_wave_wenoz_rk3_high_order(oracle_lib, axis):
+    errs = [_entropy_error(oracle_lib, N, P.WENOZ, 3, 0.05, axis=axis) for N in (16, 32, 64)]
+    r = _rates(errs)
+    assert np.all(r >= 4.5), (errs, r)
+
+
+def test_entropy_wave_ppm4_rk3_second_order(oracle_lib):
+    errs = [_entropy_error(oracle_lib, N, P.PPM4, 3, 0.05) for N in (16, 32, 64)]
+    r = _rates(errs)
+    assert np.all((r >= 1.8) & (r <= 2.3)), (errs, r)
+
+
+@pytest.mark.parametrize("recon,rk,N,cfls,lo_,hi_", [
+    (P.WENOZ, 3, 256, (0.8, 0.4), 2.75, 3.3),
+    (P.WENOZ, 2, 256, (0.8, 0.4), 1.85, 2.15),
+    (P.PLM, 1, 256, (0.4, 0.2), 0.85, 1.15),
+])
+def test_time_order_of_the_integrators(oracle_lib, recon, rk, N, cfls, lo_, hi_):
+    errs = [_entropy_error(oracle_lib, N, recon, rk, c) for c in cfls]
+    r = float(np.log2(errs[0] / errs[1]))
+    assert lo_ <= r <= hi_, (errs, r)
+
+
+@pytest.mark.parametrize("recon", [P.PLM, P.PPM4, P.WENOZ])
+@pytest.mark.parametrize("rk", [1, 2, 3])
+def test_uniform_state_preserved(oracle_lib, recon, rk):
+    # Every face sees the same two states, so L(U) = 0 exactly. RK1 and RK2
+    # then return U bitwise; RK3's stage weights 3/4 + 1/4 and 1/3 + 2/3 are
+    # not all exact in binary, so U may move by an ulp per stage, no more.
+    steps = 3
+    for bc in (P.PERIODIC, P.OUTFLOW):
+        pb = P.uniform(n=(8, 6, 7), rho=1.7, v=(0.4, -0.3, 0.25), p=0.9, bc=bc)
+        r = oracle_lib.advance(pb.with_(recon=recon, rk=rk), steps)
+        assert r["status"] == 0
+        if rk < 3:
+            assert np.array_equal(r["U"], pb.U)
+        else:
+            ulp = np.spacing(np.abs(pb.U))
+            assert np.all(np.abs(r["U"] - pb.U) <= 2 * rk * steps * ulp)
+
+
+@pytest.mark.parametrize("recon,rk", [(P.WENOZ, 3), (P.WENOZ, 2), (P.PPM4, 3), (P.PLM, 1)])
+def test_periodic_conservation_all_schemes(oracle_lib, recon, rk):
+    pb = P.turbulence(N=16, seed=31, kmax=5).with_(recon=recon, rk=rk)
+    steps = 4
+    r = oracle_lib.advance(pb, steps)
+    assert r["status"] == 0
+    eps = np.finfo(np.float64).eps
+    bound = 4 * eps * np.sqrt(pb.cells * rk * steps)
+    for v in range(5):
+        scale = np.abs(pb.U[v]).sum() + np.abs(r["U"][v]).sum()
+        assert abs(r["U"][v].sum() - pb.U[v].sum()) <= bound * scale, v
+    assert np.abs(r["U"] - pb.U).max() > 1e-3
+
+
+# ------------------------------------------------------------ Shu-Osher (Fig. 2)
+@pytest.mark.slow
+def test_shu_osher_wenoz_resolves_entropy_waves(oracle_lib):
+    t_end = 1.8
+    ref = _run_to(oracle_lib, P.shu_osher(N=800).with_(recon=P.WENOZ, rk=3), t_end)
+    rho_ref = ref[0, 0, 0].reshape(200, 4).mean(axis=1)
+    x = -5.0 + (np.arange(200) + 0.5) * 0.05
+    win = (x > 0.5) & (x < 2.2)  # the post-shock entropy waves, shock excluded
+    res = {}
+    for recon, rk in ((P.WENOZ, 3), (P.PLM, 2)):
+        rho = _run_to(oracle_lib, P.shu_osher(N=200).with_(recon=recon, rk=rk), t_end)[0, 0, 0]
+        res[recon] = (np.abs(rho - rho_ref)[win].mean(), np.ptp(rho[win]))
+    assert res[P.WENOZ][0] <= 0.9 * res[P.PLM][0], res
+    assert res[P.WENOZ][1] >= 1.2 * res[P.PLM][1], res
+
+
+# ------------------------------------------------------------ Sod, exact solution
+@pytest.mark.parametrize("recon,rk", [(P.WENOZ, 3), (P.PPM4, 3)])
+def test_sod_high_order_schemes_match_exact(oracle_lib, recon, rk):
+    import exact
+    gamma = 1.4
+    errs = []
+    for N in (64, 128, 256):
+        pb = P.sod(N=N, axis=0, ntrans=1, gamma=gamma).with_(recon=recon, rk=rk)
+        rho = _run_to(oracle_lib, pb, 0.2)[0, 0, 0]
+        errs.append(np.abs(rho - exact.cell_average_sod(N, 0.2, gamma)).mean())
+    assert np.all(np.array(errs[:-1]) / np.array(errs[1:]) > 1.3), errs
+    assert errs[-1] < 3e-3, errs
+    # the star plateaus at N = 256, as for PLM + RK2
+    ps, us = exact.star_state((1, 0, 1), (0.125, 0, 0.1), gamma)
+    rsl, rsr = exact.star_densities((1, 0, 1), (0.125, 0, 0.1), gamma)
+    x = (np.arange(256) + 0.5) / 256
+    xi = (x - 0.5) / 0.2
+    ss = us * rsr / (rsr - 0.125)
+    left = (xi > us - np.sqrt(gamma * ps / rsl) + 0.15) & (xi < us - 0.15)
+    right = (xi > us + 0.15) & (xi < ss - 0.15)
+    assert np.all(np.abs(rho[left] / rsl - 1) < 0.01)
+    assert np.all(np.abs(rho[right] / rsr - 1) < 0.01)

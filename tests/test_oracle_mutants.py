@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+import test_oracle_f2 as f2
 import test_oracle_fofc as fofc
 import test_oracle_physics as phys
 import test_oracle_units as units
@@ -36,8 +37,15 @@ MUTANTS = [
      "l -= (Fy[ym + nx] - Fy[ym]) / p->dx[0];"),
     ("divergence_sign", "l -= (Fz[zm + (size_t)nx * ny] - Fz[zm]) / p->dx[2];",
      "l += (Fz[zm + (size_t)nx * ny] - Fz[zm]) / p->dx[2];"),
-    ("rk2_stage2_weight", "0.5 * U0[c] + 0.5 * Ust[c] + 0.5 * h * w->L[c]",
-     "0.5 * U0[c] + 0.5 * Ust[c] + h * w->L[c]"),
+    ("rk2_stage2_weight", "k.a = 0.5; k.b = 0.5; k.c = 0.5;", "k.a = 0.5; k.b = 0.5; k.c = 1.0;"),
+    ("rk3_stage2_weights", "k.a = 0.75; k.b = 0.25; k.c = 0.25;", "k.a = 0.25; k.b = 0.75; k.c = 0.25;"),
+    ("rk3_stage3_step", "k.c = 2.0 / 3.0;", "k.c = 1.0 / 3.0;"),
+    ("wenoz_linear_weights", "const double d[3] = {0.1, 0.6, 0.3};", "const double d[3] = {0.3, 0.6, 0.1};"),
+    ("wenoz_candidate_sign", "(2.0 * (w[3] - w[2]) - (w[1] - w[2])) / 6.0",
+     "(2.0 * (w[3] - w[2]) + (w[1] - w[2])) / 6.0"),
+    ("wenoz_indicator_index", "0.25 * (w[1] - w[3]) * (w[1] - w[3])", "0.25 * (w[1] - w[2]) * (w[1] - w[2])"),
+    ("wenoz_left_not_mirrored", "const double m[5] = {w[4], w[3], w[2], w[1], w[0]};",
+     "const double m[5] = {w[0], w[1], w[2], w[3], w[4]};"),
     ("ghost_periodic_offset", "return bchi == OR_PERIODIC ? c % n : n - 1;",
      "return bchi == OR_PERIODIC ? (c + 1) % n : n - 1;"),
     ("ghost_outflow_index", "return bclo == OR_PERIODIC ? ((c % n) + n) % n : 0;",
@@ -85,6 +93,11 @@ def _fast_pins(O):
     yield lambda: phys.test_shear_wave_advection(O, 0)
     yield lambda: fofc.test_llf_is_hll_with_symmetric_speeds(O, 1.4)
     yield lambda: fofc.test_fofc_restores_positivity_hypersonic_turbulence(O, P.PLM)
+    yield lambda: f2.test_wenoz_exact_for_quadratics(O)
+    yield lambda: f2.test_wenoz_matches_its_definition(O)
+    yield lambda: f2.test_wenoz_fifth_order_on_smooth_data(O)
+    yield lambda: f2.test_wenoz_takes_the_smooth_side_of_a_jump(O)
+    yield lambda: f2.test_time_order_of_the_integrators(O, P.WENOZ, 3, 256, (0.8, 0.4), 2.75, 3.3)
 
 
 def test_unplanted_build_passes_fast_pins(tmp_path):
