@@ -9,10 +9,11 @@
  * equal MeshBlocks that are processed together as one MeshBlockPack
  * (Sec. 2, "MeshBlockPacks"; "Data locality"). Each step runs the paper's
  * reconstruct-solve-advance sequence (Sec. 3): ghost zones (Sec. 2,
- * "Boundary conditions"), cons-to-prim, PLM or PPM4 reconstruction on
- * primitives, HLLC fluxes in x, y and z, flux divergence and a two-stage
- * low-storage SSP Runge-Kutta update (method of lines), then the CFL time step
- * of Sec. 3, Eq. 3 taken as a minimum over all cells and dimensions.
+ * "Boundary conditions"), cons-to-prim, PLM, PPM4 or WENO-Z reconstruction
+ * on primitives, HLLC fluxes in x, y and z, flux divergence and a two- or
+ * three-stage low-storage SSP Runge-Kutta update (method of lines), then the
+ * CFL time step of Sec. 3, Eq. 3 taken as a minimum over all cells and
+ * dimensions.
  *
  * Conventions for every call:
  *  - Status codes are returned; nothing throws or aborts across the ABI.
@@ -50,20 +51,24 @@ typedef enum {
 } hy_status;
 
 enum { HY_BC_PERIODIC = 0, HY_BC_OUTFLOW = 1 };
-enum { HY_PLM = 0, HY_PPM4 = 1 };
+enum { HY_PLM = 0, HY_PPM4 = 1, HY_WENOZ = 2 };
 enum { HY_FP64 = 0, HY_MIXED = 1 };
 
 /* Problem definition (Sec. 2 mesh and boundaries; Sec. 3 algorithms).
  *  n[3]        global interior cells (nx, ny, nz), each >= 1.
  *  block[3]    MeshBlock interior size; must divide n and be >= the ghost
- *              depth (2 for PLM, 3 for PPM4).
+ *              depth (2 for PLM, 3 for PPM4 and WENO-Z).
  *  lo[3],hi[3] domain extents; dx_d = (hi_d - lo_d) / n_d > 0.
  *  bc[3][2]    lower/upper boundary per axis: HY_BC_PERIODIC (both sides of
  *              an axis must then be periodic) or HY_BC_OUTFLOW (zero-gradient
  *              copy of the nearest interior cell).
  *  gamma > 1; cfl in (0, 1].
- *  recon       HY_PLM (van Leer limited slopes) or HY_PPM4 (Colella &
- *              Woodward 1984 limiters), both on primitive variables.
+ *  recon       HY_PLM (van Leer limited slopes), HY_PPM4 (Colella &
+ *              Woodward 1984 limiters) or HY_WENOZ (fifth-order WENO-Z:
+ *              Jiang-Shu smoothness indicators, weights
+ *              d_k (1 + (tau5 / (beta_k + 1e-36))^2) with the ratio capped at
+ *              1e15, linear weights 1/10, 6/10, 3/10), all on primitive
+ *              variables.
  *  precision   HY_FP64 (all arithmetic in FP64) or HY_MIXED (reconstruction
  *              and the Riemann solve in FP32; cons-to-prim, flux divergence,
  *              the RK accumulation and the time step in FP64; U stays FP64).
@@ -71,7 +76,10 @@ enum { HY_FP64 = 0, HY_MIXED = 1 };
  *              a cell whose updated density or pressure is not positive has
  *              the fluxes on all its faces replaced by LLF fluxes of the
  *              first-order states and its stage update recomputed; 0: off.
- *              Adds 4 bytes per cell to the workspace.
+ *              Adds 1 byte per cell to the workspace.
+ *  rk          stages of the low-storage SSP Runge-Kutta integrator (Sec. 3):
+ *              2 (SSPRK(2,2)) or 3 (SSPRK(3,3)); 0 selects 2. RK3 adds a
+ *              third state register to the workspace.
  *  rho_floor, p_floor  floors applied to the primitive state only (U is
  *              never modified by a floor); each firing is counted.          */
 typedef struct {
@@ -84,12 +92,13 @@ typedef struct {
   int32_t recon;
   int32_t precision;
   int32_t fofc;
+  int32_t rk;
   double rho_floor, p_floor;
 } hy_config;
 
 /* Device bytes one problem needs: two FP64 state registers of 5 x cells
- * doubles each (the step-start state and the RK stage state), a 512-byte
- * header, and with fofc one 32-bit tag per cell. Returns 0 for an invalid
+ * doubles each (the step-start state and the RK stage state; three with
+ * rk = 3), a 512-byte header, and with fofc one byte of flag per cell. Returns 0 for an invalid
  * configuration. */
 size_t hy_workspace_bytes(const hy_config* cfg);
 
@@ -180,8 +189,9 @@ hy_status hy_get_launch(const hy_problem* p, int32_t* variant, int32_t* kc);
  * own state, keep the fastest for this problem and cache it for its (block
  * size, recon, precision) class. With full_steps == 0 only stage-1 launches
  * are timed, which leave the state unchanged; with full_steps > 0 each
- * candidate runs that many complete RK2 steps after one warm-up step, which
- * ADVANCES the state (tune a scratch copy). Synchronous. Returns the chosen
+ * candidate runs that many complete RK steps (FOFC and counters included)
+ * after one warm-up step, which ADVANCES the state (tune a scratch copy).
+ * Synchronous. Returns the chosen
  * shape in *variant/*kc (either may be NULL) and its time per stage in
  * *us_per_stage. */
 hy_status hy_autotune(hy_problem* p, void* hip_stream, int32_t full_steps, int32_t* variant,
@@ -193,10 +203,11 @@ hy_status hy_autotune(hy_problem* p, void* hip_stream, int32_t full_steps, int32
  * achievable bandwidth. */
 hy_status hy_copy_probe(void* dst, const void* src, size_t bytes, void* hip_stream);
 
-/* Record a HIP event pair around hy_advance launches: hy_advance_timed runs
- * nsteps steps on the stream and returns the elapsed device time of the
- * stage-1 and stage-2 launches separately (milliseconds), measured with HIP
- * events recorded on that same stream. Synchronous. */
+/* Record HIP events around hy_advance launches: hy_advance_timed runs nsteps
+ * steps on the stream and returns the elapsed device time of the first RK
+ * stage's launches and of the later stages' launches (stage 2, and stage 3
+ * with RK3) separately (milliseconds), measured with HIP events recorded on
+ * that same stream. Synchronous. */
 hy_status hy_advance_timed(hy_problem* p, int32_t nsteps, void* hip_stream, double* ms_stage1,
                            double* ms_stage2);
 

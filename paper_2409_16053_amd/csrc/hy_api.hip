@@ -1,7 +1,7 @@
 // hy_api.hip -- host runtime behind the C ABI of include/hy.h.
 //
 // Owns host metadata only: the problem's workspace (two FP64 MeshBlockPack
-// registers and a 512-byte header) is provided by the caller. Launch planning
+// registers, three for RK3, and a 512-byte header) is provided by the caller. Launch planning
 // turns a set of problems into per-stage launch arguments: every problem's
 // MeshBlocks are cut into x-y tiles and z-chunks, and one launch per RK
 // stage covers the tiles of all problems that share a compiled kernel
@@ -57,18 +57,24 @@ constexpr unsigned long long kInf = 0x7FF0000000000000ull;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int ghost_depth(int recon) { return recon == HY_PPM4 ? 3 : 2; }
+int ghost_depth(int recon) { return recon == HY_PLM ? 2 : 3; }
+
+int stages_of(const hy_config* c) { return c->rk == 3 ? 3 : 2; }
 
 bool validate(const hy_config* c, std::string& msg) {
   if (!c) { msg = "config is NULL"; return false; }
-  if (c->recon != HY_PLM && c->recon != HY_PPM4) { msg = "recon must be HY_PLM or HY_PPM4"; return false; }
+  if (c->recon != HY_PLM && c->recon != HY_PPM4 && c->recon != HY_WENOZ) {
+    msg = "recon must be HY_PLM, HY_PPM4 or HY_WENOZ";
+    return false;
+  }
+  if (c->rk != 0 && c->rk != 2 && c->rk != 3) { msg = "rk must be 2 or 3 (0 selects 2)"; return false; }
   if (c->precision != HY_FP64 && c->precision != HY_MIXED) { msg = "precision must be HY_FP64 or HY_MIXED"; return false; }
   if (c->fofc != 0 && c->fofc != 1) { msg = "fofc must be 0 or 1"; return false; }
   const int ng = ghost_depth(c->recon);
   for (int d = 0; d < 3; ++d) {
     if (c->n[d] < 1 || c->block[d] < 1) { msg = "n and block must be >= 1"; return false; }
     if (c->n[d] % c->block[d]) { msg = "block must divide n on every axis"; return false; }
-    if (c->block[d] < ng) { msg = "block must be >= the ghost depth (2 PLM, 3 PPM4)"; return false; }
+    if (c->block[d] < ng) { msg = "block must be >= the ghost depth (2 PLM, 3 PPM4/WENO-Z)"; return false; }
     if (!(c->hi[d] > c->lo[d]) || !std::isfinite(c->hi[d] - c->lo[d])) { msg = "need hi > lo"; return false; }
     for (int s = 0; s < 2; ++s)
       if (c->bc[d][s] != HY_BC_PERIODIC && c->bc[d][s] != HY_BC_OUTFLOW) { msg = "bad boundary code"; return false; }
@@ -85,7 +91,7 @@ bool validate(const hy_config* c, std::string& msg) {
     return false;
   }
   const double cells = (double)c->n[0] * c->n[1] * c->n[2];
-  if (cells * 5.0 * 8.0 * 2.0 > 4.0e12) { msg = "mesh too large"; return false; }
+  if (cells * 5.0 * 8.0 * stages_of(c) > 4.0e12) { msg = "mesh too large"; return false; }
   const double blk = (double)c->block[0] * c->block[1] * c->block[2] * 5.0;
   if (blk > 2.0e9) { msg = "MeshBlock too large"; return false; }
   return true;
@@ -95,8 +101,8 @@ size_t reg_bytes(const hy_config* c) {
   return align256((size_t)c->n[0] * c->n[1] * c->n[2] * 5 * sizeof(double));
 }
 
-size_t tag_bytes(const hy_config* c) {
-  return c->fofc ? align256((size_t)c->n[0] * c->n[1] * c->n[2] * sizeof(uint32_t)) : 0;
+size_t flag_bytes(const hy_config* c) {
+  return c->fofc ? align256((size_t)c->n[0] * c->n[1] * c->n[2] * sizeof(uint8_t)) : 0;
 }
 
 // Tuned launch shapes per (block size, recon, precision).
@@ -183,6 +189,7 @@ std::vector<Plan> make_plans(hy_problem* const* ps, int32_t n) {
 
 hy_status launch_group(hy_problem* const* ps, const std::vector<int>& act, const Plan& pl,
                        int stage, const std::vector<int64_t>& step_of, int flags, hipStream_t s) {
+  // every problem in `act` has at least `stage` stages
   int tx, ty;
   stage_variant_shape(pl.variant, &tx, &ty);
   for (size_t c0 = 0; c0 < act.size(); c0 += kMaxBatch) {
@@ -202,13 +209,14 @@ hy_status launch_group(hy_problem* const* ps, const std::vector<int>& act, const
       e.ntz = (p->cfg.block[2] + e.kc - 1) / e.kc;
       e.parity = (int32_t)(step_of[q] & 1);
       e.flags = flags;
-      e.tag = (uint32_t)(2 * step_of[q] + stage);
+      e.seq = (uint32_t)(p->hp.nstages * step_of[q] + stage - 1);
+      e.stage = stage;
       tiles += (int64_t)p->nblk[0] * p->nblk[1] * p->nblk[2] * e.ntx * e.nty * e.ntz;
     }
     if (tiles > 0x7fffffff) return fail(HY_ERR_ARG, "too many tiles in one launch");
     a.ntiles = (int32_t)tiles;
     if (tiles == 0) continue;
-    HY_HIP(launch_stage(pl.variant, pl.recon, pl.prec, stage, a, (int)tiles, s));
+    HY_HIP(launch_stage(pl.variant, pl.recon, pl.prec, stage == 1 ? 1 : 2, a, (int)tiles, s));
   }
   return HY_OK;
 }
@@ -222,14 +230,16 @@ hy_status launch_fix(hy_problem* const* ps, const std::vector<int>& act, const P
   for (size_t c0 = 0; c0 < f.size(); c0 += kMaxBatch) {
     FixArgs a;
     std::memset(&a, 0, sizeof a);
-    a.stage = stage;
     int grid = 1;
     for (size_t c = c0; c < std::min(f.size(), c0 + (size_t)kMaxBatch); ++c) {
       const hy_problem* p = ps[f[c]];
       FixEntry& e = a.e[a.nprob++];
       e.p = p->dp;
-      e.tag = (uint32_t)(2 * step_of[f[c]] + stage);
+      e.seq = (uint32_t)(p->hp.nstages * step_of[f[c]] + stage - 1);
       e.parity = (int32_t)(step_of[f[c]] & 1);
+      e.stage = stage;
+      e.last = stage == p->hp.nstages;
+      a.any_last |= e.last;
       grid = std::max(grid, fofc_grid(p->hp.nblocks, p->cfg.block[2]));
     }
     HY_HIP(launch_fofc(pl.recon, pl.prec, a, std::min(grid, 65535), s));
@@ -248,21 +258,27 @@ hy_status run_batch(hy_problem* const* ps, const int32_t* nsteps, int32_t n, hip
   if (dev != ps[0]->device) return fail(HY_ERR_ARG, "current device differs from the problems' device");
   const std::vector<Plan> plans = make_plans(ps, n);
   int32_t maxs = 0;
-  for (int q = 0; q < n; ++q) maxs = std::max(maxs, nsteps[q]);
+  int maxst = 0;
+  for (int q = 0; q < n; ++q) {
+    maxs = std::max(maxs, nsteps[q]);
+    maxst = std::max(maxst, ps[q]->hp.nstages);
+  }
   std::vector<int64_t> step_of(n);
   for (int q = 0; q < n; ++q) step_of[q] = ps[q]->steps;
   size_t evi = 0;
   if (ev) HY_HIP(hipEventRecord((*ev)[evi++], s));
   for (int32_t k = 0; k < maxs; ++k) {
-    for (int stage = 1; stage <= 2; ++stage) {
+    for (int stage = 1; stage <= maxst; ++stage) {
       for (const Plan& pl : plans) {
         std::vector<int> act;
         for (int q : pl.idx)
-          if (nsteps[q] > k) act.push_back(q);
+          if (nsteps[q] > k && ps[q]->hp.nstages >= stage) act.push_back(q);
         st = launch_group(ps, act, pl, stage, step_of, flags, s);
         if (st != HY_OK) return st;
-        st = launch_fix(ps, act, pl, stage, step_of, s);
-        if (st != HY_OK) return st;
+        if (flags & 1) {  // FOFC belongs to counted (real) stages only
+          st = launch_fix(ps, act, pl, stage, step_of, s);
+          if (st != HY_OK) return st;
+        }
       }
       if (ev) HY_HIP(hipEventRecord((*ev)[evi++], s));
     }
@@ -331,7 +347,7 @@ size_t hy_workspace_bytes(const hy_config* cfg) {
     g_err = msg;
     return 0;
   }
-  return (size_t)kHeaderBytes + 2 * reg_bytes(cfg) + tag_bytes(cfg);
+  return (size_t)kHeaderBytes + (size_t)stages_of(cfg) * reg_bytes(cfg) + flag_bytes(cfg);
 }
 
 hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_problem** out) {
@@ -391,9 +407,34 @@ hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_prob
   h.rho_floor = cfg->rho_floor;
   h.p_floor = cfg->p_floor;
   h.fofc = cfg->fofc;
-  h.tags = cfg->fofc ? (uint32_t*)(p->ws + kHeaderBytes + 2 * reg_bytes(cfg)) : nullptr;
+  const int nst = stages_of(cfg);
+  h.W = nst == 3 ? (double*)(p->ws + kHeaderBytes + 2 * reg_bytes(cfg)) : nullptr;
+  h.flags = cfg->fofc ? (uint8_t*)(p->ws + kHeaderBytes + (size_t)nst * reg_bytes(cfg)) : nullptr;
   h.fofc_cnt = p->dc->fofc_cnt;
   h.fofc_total = &p->dc->fofc_total;
+  // low-storage SSP-RK stages: dst = a U + b src + c dt L(src)
+  h.nstages = nst;
+  h.src[0] = h.U;
+  h.dst[0] = h.V;
+  h.rk_a[0] = 0.0;
+  h.rk_b[0] = 1.0;
+  h.rk_c[0] = 1.0;
+  if (nst == 2) {  // SSPRK(2,2)
+    h.src[1] = h.V;
+    h.dst[1] = h.U;
+    h.rk_a[1] = h.rk_b[1] = h.rk_c[1] = 0.5;
+  } else {         // SSPRK(3,3) of Shu & Osher
+    h.src[1] = h.V;
+    h.dst[1] = h.W;
+    h.rk_a[1] = 0.75;
+    h.rk_b[1] = 0.25;
+    h.rk_c[1] = 0.25;
+    h.src[2] = h.W;
+    h.dst[2] = h.U;
+    h.rk_a[2] = 1.0 / 3.0;
+    h.rk_b[2] = 2.0 / 3.0;
+    h.rk_c[2] = 2.0 / 3.0;
+  }
 
   unsigned char hdr[kHeaderBytes];
   std::memset(hdr, 0, sizeof hdr);
@@ -403,7 +444,7 @@ hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_prob
   c.dtmin[0] = c.dtmin[1] = kInf;
   std::memcpy(hdr + sizeof(DevProblem), &c, sizeof c);
   if (hipMemcpy(p->ws, hdr, sizeof hdr, hipMemcpyHostToDevice) != hipSuccess ||
-      (cfg->fofc && hipMemset(h.tags, 0, tag_bytes(cfg)) != hipSuccess)) {
+      (cfg->fofc && hipMemset(h.flags, 0, flag_bytes(cfg)) != hipSuccess)) {
     delete p;
     return fail(HY_ERR_HIP, "header upload failed");
   }
@@ -614,11 +655,11 @@ hy_status hy_autotune(hy_problem* p, void* stream, int32_t full_steps, int32_t* 
       const int reps = full_steps > 0 ? full_steps : 3;
       if (full_steps > 0) {
         int32_t one = 1;
-        st = run_batch(ps, &one, 1, s, nullptr, 0);  // warm-up step
+        st = run_batch(ps, &one, 1, s, nullptr, 1);  // warm-up step
         if (st != HY_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) { st = fail(HY_ERR_HIP, "event record"); break; }
         int32_t n = full_steps;
-        st = run_batch(ps, &n, 1, s, nullptr, 0);
+        st = run_batch(ps, &n, 1, s, nullptr, 1);
       } else {
         st = launch_group(ps, act, pl, 1, step_of, 0, s);  // warm-up
         if (st != HY_OK) break;
@@ -652,7 +693,7 @@ hy_status hy_autotune(hy_problem* p, void* stream, int32_t full_steps, int32_t* 
   }
   if (variant) *variant = bv;
   if (kc) *kc = bk;
-  if (us) *us = best * 1000.0 / (full_steps > 0 ? 2.0 * full_steps : 3.0);
+  if (us) *us = best * 1000.0 / (full_steps > 0 ? (double)p->hp.nstages * full_steps : 3.0);
   return HY_OK;
 }
 
@@ -666,17 +707,18 @@ hy_status hy_copy_probe(void* dst, const void* src, size_t bytes, void* stream) 
 hy_status hy_advance_timed(hy_problem* p, int32_t nsteps, void* stream, double* ms1, double* ms2) {
   if (!p || nsteps < 0) return fail(HY_ERR_ARG, "bad argument");
   hipStream_t s = (hipStream_t)stream;
-  std::vector<hipEvent_t> ev(2 * (size_t)nsteps + 1);
+  const size_t ns = (size_t)p->hp.nstages;
+  std::vector<hipEvent_t> ev(ns * (size_t)nsteps + 1);
   for (auto& e : ev) HY_HIP(hipEventCreate(&e));
   hy_status st = run_batch(&p, &nsteps, 1, s, &ev, 1);
   double a = 0, b = 0;
   if (st == HY_OK && hipEventSynchronize(ev.back()) == hipSuccess) {
-    for (int k = 0; k < nsteps; ++k) {
-      float x = 0, y = 0;
-      (void)hipEventElapsedTime(&x, ev[2 * k], ev[2 * k + 1]);
-      (void)hipEventElapsedTime(&y, ev[2 * k + 1], ev[2 * k + 2]);
-      a += x;
-      b += y;
+    for (size_t k = 0; k < (size_t)nsteps; ++k) {
+      for (size_t j = 0; j < ns; ++j) {
+        float x = 0;
+        (void)hipEventElapsedTime(&x, ev[ns * k + j], ev[ns * k + j + 1]);
+        (j == 0 ? a : b) += x;
+      }
     }
   }
   for (auto& e : ev) (void)hipEventDestroy(e);

@@ -2,7 +2,7 @@
 //
 // A problem's device workspace starts with a 512-byte header: the descriptor
 // below (read by every workgroup with scalar loads) and its counters. Two FP64
-// state registers follow, each a MeshBlockPack laid out as
+// state registers follow (three for RK3), each a MeshBlockPack laid out as
 // [block m][variable v][k][j][i] with i (x) fastest and no ghost cells:
 // ghost zones are filled into each tile's LDS halo directly from the
 // neighbouring block's interior or from the physical boundary condition.
@@ -20,6 +20,7 @@ constexpr int kWave = 64;       // CDNA wavefront width
 struct DevProblem {
   double* U;                 // register A: state at the start of a step / result
   double* V;                 // register B: state after RK stage 1 (and staging)
+  double* W;                 // register C: state after RK3 stage 2 (RK3 only)
   unsigned long long* dtmin; // [2] min over cells of dx_d/lambda_d as ordered bits
   double* time;              // simulation time
   unsigned long long* floor_hits;
@@ -32,10 +33,17 @@ struct DevProblem {
   int64_t bstride;           // doubles per block (5 * vstride)
   double dx[3];
   double gamma, cfl, rho_floor, p_floor;
-  uint32_t* tags;            // per-cell FOFC tag (cell flagged in stage `tag`)
-  unsigned long long* fofc_cnt;  // [2] cells flagged in the stages of tag parity 0/1
+  uint8_t* flags;            // per-cell FOFC flag of the latest counted stage
+  unsigned long long* fofc_cnt;  // [2] cells flagged in the stages of sequence parity 0/1
   unsigned long long* fofc_total;
   int32_t fofc;              // 1: first-order flux correction enabled
+  // Low-storage SSP-RK stage s (1-based) forms
+  //   dst[s-1] = a[s-1] U + b[s-1] src[s-1] + c[s-1] dt L(src[s-1])
+  // (stage 1 has a = 0, b = c = 1 and is evaluated as src + dt L).
+  int32_t nstages;           // 2 or 3
+  const double* src[3];
+  double* dst[3];
+  double rk_a[3], rk_b[3], rk_c[3];
 };
 
 // Counters that follow the descriptor in the header.
@@ -59,7 +67,9 @@ struct BatchEntry {
   int32_t kc;       // planes per z-chunk
   int32_t parity;   // step index mod 2: which dtmin slot the step reads
   int32_t flags;    // bit 0: count floors, flag bad states, flag FOFC cells
-  uint32_t tag;     // 2 * step + stage: FOFC tag of this stage (never 0)
+  uint32_t seq;     // nstages * step + stage - 1: running stage number (parity
+                    // selects the FOFC counter slot)
+  int32_t stage;    // RK stage, 1-based
 };
 
 struct StageArgs {
@@ -73,13 +83,15 @@ static_assert(sizeof(StageArgs) <= 3072, "kernel arguments too large");
 // First-order flux correction pass after a stage (problems with fofc on).
 struct FixEntry {
   const DevProblem* p;
-  uint32_t tag;
+  uint32_t seq;
   int32_t parity;
+  int32_t stage;    // RK stage, 1-based
+  int32_t last;     // 1 if this is the problem's last stage (time step follows)
 };
 
 struct FixArgs {
   int32_t nprob;
-  int32_t stage;
+  int32_t any_last; // 1 if some entry is at its last stage
   FixEntry e[kMaxBatch];
 };
 

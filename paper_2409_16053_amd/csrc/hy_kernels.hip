@@ -2,9 +2,10 @@
 //
 // One fused kernel per RK stage performs the whole reconstruct-solve-advance
 // sequence of Stone et al. 2024 (arXiv:2409.16053), Sec. 3: ghost zones,
-// cons-to-prim (Sec. 3.1, Eq. 4), PLM or PPM4 reconstruction on primitives,
-// HLLC fluxes in x, y and z, the flux divergence and the SSP-RK2 stage
-// update; stage 2 also reduces the CFL time step of Sec. 3, Eq. 3.
+// cons-to-prim (Sec. 3.1, Eq. 4), PLM, PPM4 or WENO-Z reconstruction on
+// primitives, HLLC fluxes in x, y and z, the flux divergence and the
+// low-storage SSP-RK stage update; the last stage also reduces the CFL time
+// step of Sec. 3, Eq. 3.
 //
 // Work decomposition. A workgroup owns an x-y tile (TX x TY columns) of one
 // MeshBlock and marches along z through a chunk of planes. Each owned column
@@ -116,6 +117,70 @@ __device__ __forceinline__ void ppm_mono(T a, T& aL, T& aR) {
   const T nR = over_r ? T(3) * a - T(2) * aL : aR;
   aL = ext ? a : nL;
   aR = ext ? a : nR;
+}
+
+// WENO-Z (Sec. 3; Borges et al. 2008 weights on the Jiang-Shu smoothness
+// indicators). From the cells (w0..w4) = c-2..c+2: the three third-order
+// candidate values of the right face of cell c, written as differences from
+// w2 (times 6) so that a constant state is reproduced exactly, weighted by
+// alpha_k = d_k (1 + r_k^2), r_k = min(tau5 / (beta_k + eps), 1e15),
+// tau5 = |beta_0 - beta_2|, d = (1, 6, 3)/10. The cap keeps the weights finite
+// in FP32 and changes them only where one candidate already has weight 1 to
+// within 1e-30.
+template <typename T>
+struct WenoInd {
+  T b0, b1, b2;
+};
+
+template <typename T>
+__device__ __forceinline__ WenoInd<T> weno_ind(T w0, T w1, T w2, T w3, T w4) {
+  const T e0 = w0 - T(2) * w1 + w2, f0 = w0 - T(4) * w1 + T(3) * w2;
+  const T e1 = w1 - T(2) * w2 + w3, f1 = w1 - w3;
+  const T e2 = w2 - T(2) * w3 + w4, f2 = T(3) * w2 - T(4) * w3 + w4;
+  const T c13 = T(13.0 / 12.0);
+  return WenoInd<T>{c13 * e0 * e0 + T(0.25) * f0 * f0, c13 * e1 * e1 + T(0.25) * f1 * f1,
+                    c13 * e2 * e2 + T(0.25) * f2 * f2};
+}
+
+// Weighted sum of the candidates (given as 6 x difference from wc) with the
+// indicators ordered as the candidates.
+template <typename T>
+__device__ __forceinline__ T weno_mix(T wc, T q0, T q1, T q2, T b0, T b1, T b2) {
+  const T eps = T(1e-36), cap = T(1e15);
+  const T tau = fabs(b0 - b2);
+  const T r0 = fmin(tau * rcp(b0 + eps), cap);
+  const T r1 = fmin(tau * rcp(b1 + eps), cap);
+  const T r2 = fmin(tau * rcp(b2 + eps), cap);
+  const T a0 = T(0.1) * (T(1) + r0 * r0);
+  const T a1 = T(0.6) * (T(1) + r1 * r1);
+  const T a2 = T(0.3) * (T(1) + r2 * r2);
+  // normalise the weights first: a_k can reach 1e30, which must not meet a
+  // large candidate in FP32
+  const T id = rcp((a0 + a1) + a2);
+  const T mix = ((a0 * id) * q0 + (a1 * id) * q1) + (a2 * id) * q2;
+  return wc + mix * T(1.0 / 6.0);
+}
+
+// Right face value of the middle cell of (w0..w4).
+template <typename T>
+__device__ __forceinline__ T weno_right(T w0, T w1, T w2, T w3, T w4) {
+  const WenoInd<T> b = weno_ind(w0, w1, w2, w3, w4);
+  const T q0 = T(2) * (w0 - w1) - T(5) * (w1 - w2);
+  const T q1 = T(2) * (w3 - w2) - (w1 - w2);
+  const T q2 = T(4) * (w3 - w2) - (w4 - w3);
+  return weno_mix(w2, q0, q1, q2, b.b0, b.b1, b.b2);
+}
+
+// Both face values of the middle cell, sharing the indicators: the left face
+// is the right-face formula on the mirrored stencil, whose indicators are
+// (beta_2, beta_1, beta_0).
+template <typename T>
+__device__ __forceinline__ void weno_cell(T w0, T w1, T w2, T w3, T w4, T& left, T& right) {
+  const WenoInd<T> b = weno_ind(w0, w1, w2, w3, w4);
+  right = weno_mix(w2, T(2) * (w0 - w1) - T(5) * (w1 - w2), T(2) * (w3 - w2) - (w1 - w2),
+                   T(4) * (w3 - w2) - (w4 - w3), b.b0, b.b1, b.b2);
+  left = weno_mix(w2, T(2) * (w4 - w3) - T(5) * (w3 - w2), T(2) * (w1 - w2) - (w3 - w2),
+                  T(4) * (w1 - w2) - (w0 - w1), b.b2, b.b1, b.b0);
 }
 
 // --------------------------------------------------------------- HLLC
@@ -330,6 +395,13 @@ struct ZQueue<1, T> {       // PPM4
 };
 
 template <typename T>
+struct ZQueue<2, T> {       // WENO-Z
+  T wm[5], w0[5], w1[5], w2[5];  // primitives at k-1, k, k+1, k+2
+  T ar0[5];                 // right face value of cell k
+  double fm[5];
+};
+
+template <typename T>
 __device__ __forceinline__ void zflux(const Gas<T>& g, const T wl[5], const T wr[5], double f[5]) {
   // z-normal: (n, t1, t2) = (vz, vx, vy)
   T h[5];
@@ -344,7 +416,7 @@ __device__ __forceinline__ void zflux(const Gas<T>& g, const T wl[5], const T wr
 // ------------------------------------------------------------ one face
 // Flux through the face between LDS cells (base - STR) and base along
 // direction DIR (0 = x, 1 = y), in conserved-variable order. PLM reads two
-// cells on each side, PPM4 three.
+// cells on each side, PPM4 and WENO-Z three.
 template <int RECON, int DIR, typename T, int STR, int PLANE>
 __device__ __forceinline__ void face_flux(const Gas<T>& gas, const T* __restrict__ sW, int base,
                                           T out[5]) {
@@ -356,6 +428,11 @@ __device__ __forceinline__ void face_flux(const Gas<T>& gas, const T* __restrict
       const T c0 = s[-2 * STR], c1 = s[-STR], c2 = s[0], c3 = s[STR];
       wl[v] = c1 + T(0.5) * plm_slope(c0, c1, c2);
       wr[v] = c2 - T(0.5) * plm_slope(c1, c2, c3);
+    } else if constexpr (RECON == 2) {
+      const T c0 = s[-3 * STR], c1 = s[-2 * STR], c2 = s[-STR];
+      const T c3 = s[0], c4 = s[STR], c5 = s[2 * STR];
+      wl[v] = weno_right(c0, c1, c2, c3, c4);  // right face of cell c2
+      wr[v] = weno_right(c5, c4, c3, c2, c1);  // left face of cell c3 (mirrored)
     } else {
       const T c0 = s[-3 * STR], c1 = s[-2 * STR], c2 = s[-STR];
       const T c3 = s[0], c4 = s[STR], c5 = s[2 * STR];
@@ -383,8 +460,12 @@ __device__ __forceinline__ void face_flux(const Gas<T>& gas, const T* __restrict
 }
 
 // -------------------------------------------------------------- the stage
-// Stage 1: V = U + dt L(U).   Stage 2: U = U/2 + V/2 + dt L(V)/2, then the
-// minimum of dx_d/lambda_d over the new U for the next time step.
+// STAGE 1 (first RK stage): dst = src + dt L(src), with src the step-start
+// state U. STAGE 2 (later stages): dst = a U + b src + c dt L(src). RK2:
+// V = U + dt L(U), then U = U/2 + V/2 + dt L(V)/2. RK3: V = U + dt L(U),
+// W = 3U/4 + V/4 + dt L(V)/4, U = U/3 + 2W/3 + 2 dt L(W)/3. The last stage of
+// a problem also reduces the minimum of dx_d/lambda_d over its new U for the
+// next time step.
 template <int RECON, typename T, int TX, int TY, int WPE, int STAGE>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_stage(const StageArgs a) {
@@ -433,8 +514,11 @@ k_stage(const StageArgs a) {
     const bool own = tx < nxv && ty < nyv;
     const int gi = i0 + tx, gj = j0 + ty;  // owned column, block-local
 
-    const double* __restrict__ Sin = STAGE == 1 ? P.U : P.V;
-    double* __restrict__ Out = STAGE == 1 ? P.V : P.U;
+    const int si = E.stage - 1;
+    const double* __restrict__ Sin = P.src[si];
+    double* __restrict__ Out = P.dst[si];
+    const double ca = P.rk_a[si], cb = P.rk_b[si], cc = P.rk_c[si];
+    const bool last = E.stage == P.nstages;  // uniform over the workgroup
     const int64_t vs = geo.vstride;
 
     const double gamma = P.gamma, gm1 = gamma - 1.0;
@@ -447,8 +531,8 @@ k_stage(const StageArgs a) {
     if (STAGE == 1 && loc == 0 && tid == 0) P.dtmin[E.parity ^ 1] = kInfBits;
     const bool fofc = P.fofc && count;
     if (fofc && loc == 0 && tid == 0) {  // fold the counter of two stages ago
-      *P.fofc_total = *P.fofc_total + P.fofc_cnt[(E.tag + 1) & 1];
-      P.fofc_cnt[(E.tag + 1) & 1] = 0ull;
+      *P.fofc_total = *P.fofc_total + P.fofc_cnt[(E.seq + 1) & 1];
+      P.fofc_cnt[(E.seq + 1) & 1] = 0ull;
     }
 
     int hits = 0, bad = 0;
@@ -493,6 +577,27 @@ k_stage(const StageArgs a) {
           zq.w0[v] = wc[v];
           zq.w1[v] = wd[v];
           zq.s0[v] = sc;
+        }
+        zflux(gas, wl, wr, zq.fm);
+      } else if constexpr (RECON == 2) {
+        double u[5];
+        T c[6][5];
+#pragma unroll
+        for (int o = 0; o < 6; ++o) {
+          col_load(k0 - 3 + o, u);
+          to_prim(u, c[o], k0 - 3 + o);
+        }
+        T wl[5], wr[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          wl[v] = weno_right(c[0][v], c[1][v], c[2][v], c[3][v], c[4][v]);  // cell k0-1
+          T lk;
+          weno_cell(c[1][v], c[2][v], c[3][v], c[4][v], c[5][v], lk, zq.ar0[v]);  // cell k0
+          wr[v] = lk;
+          zq.wm[v] = c[2][v];
+          zq.w0[v] = c[3][v];
+          zq.w1[v] = c[4][v];
+          zq.w2[v] = c[5][v];
         }
         zflux(gas, wl, wr, zq.fm);
       } else {
@@ -616,6 +721,26 @@ k_stage(const StageArgs a) {
             zq.w1[v] = w2[v];
             zq.s0[v] = s1[v];
           }
+        } else if constexpr (RECON == 2) {
+          T w3[5];
+          to_prim(un, w3, k + 3);
+          T wl[5], wr[5], r1[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            T l1;
+            weno_cell(zq.wm[v], zq.w0[v], zq.w1[v], zq.w2[v], w3[v], l1, r1[v]);  // cell k+1
+            wl[v] = zq.ar0[v];
+            wr[v] = l1;
+          }
+          zflux(gas, wl, wr, fz);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            zq.wm[v] = zq.w0[v];
+            zq.w0[v] = zq.w1[v];
+            zq.w1[v] = zq.w2[v];
+            zq.w2[v] = w3[v];
+            zq.ar0[v] = r1[v];
+          }
         } else {
           T w3[5];
           to_prim(un, w3, k + 3);
@@ -663,21 +788,28 @@ k_stage(const StageArgs a) {
           if (STAGE == 1) {
             unew[v] = uc[v] + dt * l;
           } else {
-            unew[v] = (0.5 * un0[v] + 0.5 * uc[v]) + (0.5 * dt) * l;
+            unew[v] = (ca * un0[v] + cb * uc[v]) + (cc * dt) * l;
           }
           zq.fm[v] = fz[v];
         }
-#pragma unroll
-        for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(unew[v], Out + off + v * vs);
+        bool flag = false;
         if (fofc) {  // first-order flux correction: flag a non-positive result
+          // (every counted stage rewrites every flag, so no flag outlives
+          // the stage that set it)
           const double ke2 = (unew[1] * unew[1] + unew[2] * unew[2]) + unew[3] * unew[3];
           const double pn = gm1 * (unew[4] - (0.5 * ke2) * rcp(unew[0]));
-          if (!(unew[0] > 0.0) || !(pn > 0.0)) {
-            P.tags[(int64_t)m * geo.vstride + k * pstride + (int64_t)gj * geo.bx + gi] = E.tag;
-            atomicAdd(P.fofc_cnt + (E.tag & 1), 1ull);
-          }
+          flag = !(unew[0] > 0.0) || !(pn > 0.0);
+          P.flags[(int64_t)m * geo.vstride + k * pstride + (int64_t)gj * geo.bx + gi] = flag ? 1 : 0;
+          if (flag) atomicAdd(P.fofc_cnt + (E.seq & 1), 1ull);
         }
-        if (STAGE == 2) mydt = fmin(mydt, cell_dt(fl, gamma, gm1, P.dx, unew));
+        // a flagged cell is recomputed from scratch by k_fofc_fix; skipping
+        // its store keeps the step-start state in place for the last stage,
+        // which updates U in place
+        if (!flag) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(unew[v], Out + off + v * vs);
+        }
+        if (STAGE == 2 && last) mydt = fmin(mydt, cell_dt(fl, gamma, gm1, P.dx, unew));
       }
     }
 
@@ -686,7 +818,7 @@ k_stage(const StageArgs a) {
       if (hits) atomicAdd(P.floor_hits, (unsigned long long)hits);
       if (bad) atomicOr(P.err, 1u);
     }
-    if (STAGE == 2) {
+    if (STAGE == 2 && last) {
       unsigned long long b = (unsigned long long)__double_as_longlong(mydt);
 #pragma unroll
       for (int s = kWave / 2; s > 0; s >>= 1) {
@@ -738,6 +870,9 @@ __device__ void face_pair(const Geo& geo, const Floors& fl, const Gas<T>& gas,
     if constexpr (RECON == 0) {
       wl[v] = c[1][v] + T(0.5) * plm_slope(c[0][v], c[1][v], c[2][v]);
       wr[v] = c[2][v] - T(0.5) * plm_slope(c[1][v], c[2][v], c[3][v]);
+    } else if constexpr (RECON == 2) {
+      wl[v] = weno_right(c[0][v], c[1][v], c[2][v], c[3][v], c[4][v]);
+      wr[v] = weno_right(c[5][v], c[4][v], c[3][v], c[2][v], c[1][v]);
     } else {
       const T d1 = ppm_dm(c[0][v], c[1][v], c[2][v]), d2 = ppm_dm(c[1][v], c[2][v], c[3][v]);
       const T d3 = ppm_dm(c[2][v], c[3][v], c[4][v]), d4 = ppm_dm(c[3][v], c[4][v], c[5][v]);
@@ -763,29 +898,46 @@ __device__ void face_pair(const Geo& geo, const Floors& fl, const Gas<T>& gas,
   flf[0] = g[0]; flf[n] = g[1]; flf[t1] = g[2]; flf[t2] = g[3]; flf[4] = g[4];
 }
 
+// The LLF flux of the first-order states through the same face.
+template <typename T>
+__device__ void face_llf(const Geo& geo, const Floors& fl, const Gas<T>& gas,
+                         const double* __restrict__ S, int d, int i, int j, int k, T out[5]) {
+  const int di = d == 0, dj = d == 1, dk = d == 2;
+  T a[5], b[5];
+  prim_at(geo, fl, S, i - di, j - dj, k - dk, a);
+  prim_at(geo, fl, S, i, j, k, b);
+  const int n = 1 + d, t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
+  T g[5];
+  llf(gas, a[0], a[n], a[t1], a[t2], a[4], b[0], b[n], b[t1], b[t2], b[4], g);
+  out[0] = g[0]; out[n] = g[1]; out[t1] = g[2]; out[t2] = g[3]; out[4] = g[4];
+}
+
 constexpr int kFixPlanes = 4;  // z-planes of one MeshBlock per workgroup pass
 
 // Replace, for every cell flagged in this stage, the fluxes on all its faces by
-// LLF fluxes of the first-order states: each cell that is flagged or has a
-// flagged face neighbour adds (F_LLF - F_HO) of its affected faces to its
-// stage result. Exits at once when nothing was flagged. Stage 2 also resets
-// the time-step slot for k_fofc_dt.
+// LLF fluxes of the first-order states. A flagged cell (whose store the stage
+// kernel skipped) is recomputed from scratch with LLF fluxes on all six
+// faces, so a non-finite high-order flux never enters it; an unflagged cell
+// with flagged face neighbours adds c_s dt (F_LLF - F_HO) / dx of those faces
+// to its stage result (c_s is the stage's weight of dt L; every F_HO it saw
+// was finite, or its result would have been flagged). Exits at once when
+// nothing was flagged. A problem's last stage also resets the time-step slot
+// for k_fofc_dt.
 template <int RECON, typename T>
 __global__ void __launch_bounds__(256) k_fofc_fix(const FixArgs a) {
   const FixEntry E = a.e[blockIdx.y];
   const DevProblem& P = *E.p;
-  if (P.fofc_cnt[E.tag & 1] == 0ull) return;
-  const int stage = a.stage;
-  if (stage == 2 && blockIdx.x == 0 && threadIdx.x == 0) P.dtmin[E.parity ^ 1] = kInfBits;
-  const double* __restrict__ S = stage == 1 ? P.U : P.V;
-  double* __restrict__ Out = stage == 1 ? P.V : P.U;
+  if (P.fofc_cnt[E.seq & 1] == 0ull) return;
+  const int si = E.stage - 1;
+  if (E.last && blockIdx.x == 0 && threadIdx.x == 0) P.dtmin[E.parity ^ 1] = kInfBits;
+  const double* __restrict__ S = P.src[si];
+  double* Out = P.dst[si];  // is P.U itself in a problem's last stage
   const double gamma = P.gamma, gm1 = gamma - 1.0;
   const Gas<T> gas{T(gamma), T(gm1), T((gamma + 1.0) / (2.0 * gamma))};
   const Floors fl{P.rho_floor, P.p_floor / gm1};
   const double dt = P.cfl * __longlong_as_double((long long)P.dtmin[E.parity]);
-  const double cst = stage == 1 ? dt : 0.5 * dt;
+  const double cst = P.rk_c[si] * dt;
   const double id[3] = {1.0 / P.dx[0], 1.0 / P.dx[1], 1.0 / P.dx[2]};
-  const uint32_t tag = E.tag;
   const int slabs = (P.bz + kFixPlanes - 1) / kFixPlanes;
   for (int w = blockIdx.x; w < P.nblocks * slabs; w += gridDim.x) {
     const int m = w / slabs, k0 = (w - m * slabs) * kFixPlanes;
@@ -797,19 +949,51 @@ __global__ void __launch_bounds__(256) k_fofc_fix(const FixArgs a) {
       const int k = (int)(r / plane);
       const int rem = (int)(r - k * plane);
       const int j = rem / geo.bx, i = rem - j * geo.bx;
-      const bool me = P.tags[(int64_t)m * geo.vstride + r] == tag;
+      const bool me = P.flags[(int64_t)m * geo.vstride + r] != 0;
       bool nb[6];
-      nb[0] = P.tags[ghost_cell(geo, i - 1, j, k)] == tag;
-      nb[1] = P.tags[ghost_cell(geo, i + 1, j, k)] == tag;
-      nb[2] = P.tags[ghost_cell(geo, i, j - 1, k)] == tag;
-      nb[3] = P.tags[ghost_cell(geo, i, j + 1, k)] == tag;
-      nb[4] = P.tags[ghost_cell(geo, i, j, k - 1)] == tag;
-      nb[5] = P.tags[ghost_cell(geo, i, j, k + 1)] == tag;
+      nb[0] = P.flags[ghost_cell(geo, i - 1, j, k)] != 0;
+      nb[1] = P.flags[ghost_cell(geo, i + 1, j, k)] != 0;
+      nb[2] = P.flags[ghost_cell(geo, i, j - 1, k)] != 0;
+      nb[3] = P.flags[ghost_cell(geo, i, j + 1, k)] != 0;
+      nb[4] = P.flags[ghost_cell(geo, i, j, k - 1)] != 0;
+      nb[5] = P.flags[ghost_cell(geo, i, j, k + 1)] != 0;
       if (!(me || nb[0] || nb[1] || nb[2] || nb[3] || nb[4] || nb[5])) continue;
+      const int64_t off = (int64_t)m * geo.bstride + r;
+      if (me) {
+        // the stage formula with first-order LLF fluxes on every face,
+        // divergence summed in x, y, z order as in the stage kernel
+        double l[5];
+        for (int d = 0; d < 3; ++d) {
+          T flo[5], fhi[5];
+          face_llf<T>(geo, fl, gas, S, d, i, j, k, flo);
+          face_llf<T>(geo, fl, gas, S, d, i + (d == 0), j + (d == 1), k + (d == 2), fhi);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            const double df = ((double)fhi[v] - (double)flo[v]) * id[d];
+            l[v] = d == 0 ? -df : l[v] - df;
+          }
+        }
+        double us[5], unew[5];
+        load5(S, off, geo.vstride, us);
+        if (si == 0) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) unew[v] = us[v] + dt * l[v];
+        } else {
+          double u0[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) u0[v] = P.U[off + v * geo.vstride];
+          const double ca = P.rk_a[si], cb = P.rk_b[si], cc = P.rk_c[si];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) unew[v] = (ca * u0[v] + cb * us[v]) + (cc * dt) * l[v];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Out[off + v * geo.vstride] = unew[v];
+        continue;
+      }
       double dL[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
       for (int d = 0; d < 3; ++d) {
         for (int s = 0; s < 2; ++s) {
-          if (!me && !nb[2 * d + s]) continue;
+          if (!nb[2 * d + s]) continue;
           T fho[5], flf[5];
           face_pair<RECON, T>(geo, fl, gas, S, d, i + s * (d == 0), j + s * (d == 1), k + s * (d == 2),
                               fho, flf);
@@ -819,7 +1003,6 @@ __global__ void __launch_bounds__(256) k_fofc_fix(const FixArgs a) {
           for (int v = 0; v < 5; ++v) dL[v] += sg * ((double)flf[v] - (double)fho[v]);
         }
       }
-      const int64_t off = (int64_t)m * geo.bstride + r;
 #pragma unroll
       for (int v = 0; v < 5; ++v) Out[off + v * geo.vstride] += cst * dL[v];
     }
@@ -830,7 +1013,7 @@ __global__ void __launch_bounds__(256) k_fofc_fix(const FixArgs a) {
 __global__ void __launch_bounds__(256) k_fofc_dt(const FixArgs a) {
   const FixEntry E = a.e[blockIdx.y];
   const DevProblem& P = *E.p;
-  if (P.fofc_cnt[E.tag & 1] == 0ull) return;
+  if (!E.last || P.fofc_cnt[E.seq & 1] == 0ull) return;
   const double gamma = P.gamma, gm1 = gamma - 1.0;
   const Floors fl{P.rho_floor, P.p_floor / gm1};
   const int64_t ncell = (int64_t)P.nblocks * P.vstride;
@@ -945,16 +1128,16 @@ __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32
 // the register allocator targets (waves per SIMD; more waves hide latency
 // better but may force spills).
 #define HY_K(R, T, TX, TY, W, S) (const void*)&k_stage<R, T, TX, TY, W, S>
+#define HY_RECON_SET(R, TX, TY, W)                                                    \
+  {{HY_K(R, double, TX, TY, W, 1), HY_K(R, double, TX, TY, W, 2)},                    \
+   {HY_K(R, float, TX, TY, W, 1), HY_K(R, float, TX, TY, W, 2)}}
 #define HY_STAGE_SET(TX, TY, W)                                                       \
   {TX, TY, W,                                                                         \
-   {{{HY_K(0, double, TX, TY, W, 1), HY_K(0, double, TX, TY, W, 2)},                  \
-     {HY_K(0, float, TX, TY, W, 1), HY_K(0, float, TX, TY, W, 2)}},                   \
-    {{HY_K(1, double, TX, TY, W, 1), HY_K(1, double, TX, TY, W, 2)},                  \
-     {HY_K(1, float, TX, TY, W, 1), HY_K(1, float, TX, TY, W, 2)}}}}
+   {HY_RECON_SET(0, TX, TY, W), HY_RECON_SET(1, TX, TY, W), HY_RECON_SET(2, TX, TY, W)}}
 
 struct StageVariant {
   int tx, ty, wpe;
-  const void* fn[2][2][2];  // [recon][precision][stage-1]
+  const void* fn[3][2][2];  // [recon][precision][kind: first stage, later stage]
 };
 
 static const StageVariant kStageVariants[] = {
@@ -971,23 +1154,26 @@ void stage_variant_shape(int v, int* tx, int* ty) {
 
 int stage_variant_waves(int v) { return kStageVariants[v].wpe; }
 
-const void* stage_kernel(int v, int recon, int prec, int stage) {
-  return kStageVariants[v].fn[recon][prec][stage - 1];
+// kind 1: the first RK stage; kind 2: any later stage.
+const void* stage_kernel(int v, int recon, int prec, int kind) {
+  return kStageVariants[v].fn[recon][prec][kind - 1];
 }
 
-hipError_t launch_stage(int v, int recon, int prec, int stage, const StageArgs& a, int grid,
+hipError_t launch_stage(int v, int recon, int prec, int kind, const StageArgs& a, int grid,
                         hipStream_t s) {
   const StageVariant& sv = kStageVariants[v];
   void* args[] = {(void*)&a};
-  return hipLaunchKernel(sv.fn[recon][prec][stage - 1], dim3(grid), dim3(sv.tx * sv.ty), args, 0, s);
+  return hipLaunchKernel(sv.fn[recon][prec][kind - 1], dim3(grid), dim3(sv.tx * sv.ty), args, 0, s);
 }
 
 hipError_t launch_fofc(int recon, int prec, const FixArgs& a, int grid_x, hipStream_t s) {
-  static const void* fix[2][2] = {{(const void*)&k_fofc_fix<0, double>, (const void*)&k_fofc_fix<0, float>},
-                                  {(const void*)&k_fofc_fix<1, double>, (const void*)&k_fofc_fix<1, float>}};
+  static const void* fix[3][2] = {
+      {(const void*)&k_fofc_fix<0, double>, (const void*)&k_fofc_fix<0, float>},
+      {(const void*)&k_fofc_fix<1, double>, (const void*)&k_fofc_fix<1, float>},
+      {(const void*)&k_fofc_fix<2, double>, (const void*)&k_fofc_fix<2, float>}};
   void* args[] = {(void*)&a};
   hipError_t e = hipLaunchKernel(fix[recon][prec], dim3(grid_x, a.nprob), dim3(256), args, 0, s);
-  if (e != hipSuccess || a.stage != 2) return e;
+  if (e != hipSuccess || !a.any_last) return e;
   return hipLaunchKernel((const void*)&k_fofc_dt, dim3(grid_x, a.nprob), dim3(256), args, 0, s);
 }
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhy.so")
 
 HY_OK, HY_ERR_ARG, HY_ERR_NOMEM, HY_ERR_HIP, HY_ERR_STATE, HY_ERR_BUDGET = range(6)
 PERIODIC, OUTFLOW = 0, 1
-PLM, PPM4 = 0, 1
+PLM, PPM4, WENOZ = 0, 1, 2
 FP64, MIXED = 0, 1
 HOST, DEVICE, HOST_PINNED = 0, 1, 2
 
@@ -39,6 +39,7 @@ class HyConfig(_c.Structure):
         ("recon", _c.c_int32),
         ("precision", _c.c_int32),
         ("fofc", _c.c_int32),
+        ("rk", _c.c_int32),
         ("rho_floor", _c.c_double),
         ("p_floor", _c.c_double),
     ]
@@ -132,6 +133,7 @@ def make_config(pb) -> HyConfig:
     c.recon = int(pb.recon)
     c.precision = int(pb.precision)
     c.fofc = int(getattr(pb, "fofc", 0))
+    c.rk = int(getattr(pb, "rk", 2))
     c.rho_floor = float(pb.rho_floor)
     c.p_floor = float(pb.p_floor)
     return c

@@ -299,13 +299,17 @@ def kelvin_helmholtz(N=512, seed=2, n=None, gamma=5.0 / 3.0, noise=1e-2, **kw):
 # Sedov blast
 # --------------------------------------------------------------------------
 def sedov(N=32, seed=3, energy=1.0, radius_cells=3.0, rho=1.0, p=1e-5,
-          gamma=5.0 / 3.0, centre=None, **kw):
+          gamma=5.0 / 3.0, centre=None, noise=0.0, **kw):
     """Point explosion on the unit cube with outflow boundaries.
 
     Background rho = 1, p = 1e-5, v = 0. The centre is a seeded cell centre at
     least four cells from every face; ``energy`` is spread evenly, as internal
     energy, over the cells whose centres lie within ``radius_cells`` cell
     widths of it (123 cells for radius 3), replacing the background there.
+    ``noise`` > 0 multiplies the density and the pressure by independent
+    factors 1 + noise (2 r - 1), r from SplitMix64(seed, counter) with counter
+    = global cell index (density) and N^3 + global cell index (pressure),
+    which breaks the exact mirror symmetry of the blast.
     """
     if centre is None:
         rng = np.random.default_rng(seed)
@@ -321,7 +325,12 @@ def sedov(N=32, seed=3, energy=1.0, radius_cells=3.0, rho=1.0, p=1e-5,
     ncell = int(inside.sum())
     u_in = energy / (ncell * dx ** 3)
     pres = np.where(inside, (gamma - 1.0) * u_in, p)
-    U = conserved(np.full(shape, rho), 0.0, 0.0, 0.0, pres, gamma)
+    dens = np.full(shape, rho)
+    if noise > 0.0:
+        idx = np.arange(N * N * N, dtype=np.uint64).reshape(shape)
+        dens = dens * (1.0 + noise * (2.0 * uniform01(seed, idx) - 1.0))
+        pres = pres * (1.0 + noise * (2.0 * uniform01(seed, idx + np.uint64(N * N * N)) - 1.0))
+    U = conserved(dens, 0.0, 0.0, 0.0, pres, gamma)
     bcs = ((OUTFLOW, OUTFLOW),) * 3
     return Problem(n=(N, N, N), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=bcs, U=U,
                    gamma=gamma, name="sedov",

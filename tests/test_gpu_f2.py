@@ -1,0 +1,197 @@
+"""GPU parity of the higher-order options: WENO-Z reconstruction and the
+three-stage SSP-RK integrator, against the CPU reference solver.
+
+FP64 gate: rel L1 <= 1e-12 and per-variable elementwise agreement <= 1e-9 of
+the variable's largest magnitude; mixed precision: rel L1 <= 1e-5 against the
+FP64 reference.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_16053_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hy():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_16053_amd import hy as _hy
+    _hy.lib()
+    return _hy
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).sum() / np.abs(b).sum())
+
+
+def _elem(a, b):
+    scale = np.abs(b).reshape(5, -1).max(axis=1)
+    scale = np.where(scale > 0, scale, 1.0)
+    return float((np.abs(a - b).reshape(5, -1).max(axis=1) / scale).max())
+
+
+def _run(hy, pb, steps, variant=None, kc=None):
+    g = hy.Problem(pb).set_state()
+    if variant is not None:
+        g.set_launch(variant, kc)
+    g.advance(steps)
+    U, q = g.get_state(), g.query()
+    g.close()
+    return U, q
+
+
+def _check(hy, pb, steps, label, **kw):
+    print(f"[{label}] n={pb.n} block={pb.block} recon={pb.recon} rk={pb.rk} fofc={pb.fofc}",
+          flush=True)
+    U, q = _run(hy, pb, steps, **kw)
+    ref = oracle.advance(pb, steps)
+    r, e = _rel(U, ref["U"]), _elem(U, ref["U"])
+    print(f"[{label}] rel L1 {r:.3e} elem {e:.3e} dt {q['dt']:.15g}/{ref['dt']:.15g} "
+          f"floors {q['floor_hits']}/{ref['floor_hits']} fofc {q['fofc_cells']}/{ref['fofc_cells']}",
+          flush=True)
+    assert r <= 1e-12 and e <= 1e-9
+    assert abs(q["dt"] / ref["dt"] - 1) <= 1e-11
+    assert abs(q["t"] - ref["t"]) <= 1e-13 * max(1.0, abs(ref["t"]))
+    assert q["floor_hits"] == ref["floor_hits"] and q["fofc_cells"] == ref["fofc_cells"]
+    return U, q, ref
+
+
+@pytest.mark.parametrize("recon,rk", [(P.WENOZ, 3), (P.WENOZ, 2), (P.PLM, 3), (P.PPM4, 3)])
+def test_turbulence_schemes(hy, recon, rk):
+    pb = P.turbulence(N=48, seed=3, kmax=8).with_(block=(16, 16, 24), recon=recon, rk=rk)
+    _check(hy, pb, 8, f"turb {recon}/{rk}")
+
+
+def test_kh_wenoz_rk3_ragged_tiles(hy):
+    # 40 x 24 x 24 blocks: no tile shape divides 40, so the x tiles are ragged
+    pb = P.kelvin_helmholtz(n=(80, 48, 24), seed=5).with_(block=(40, 24, 24), recon=P.WENOZ, rk=3)
+    _check(hy, pb, 6, "kh wenoz ragged")
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_sod_wenoz_rk3_each_axis(hy, axis):
+    pb = P.sod(N=64, axis=axis, ntrans=8).with_(block=(8, 8, 8), recon=P.WENOZ, rk=3)
+    pb = pb.with_(block=tuple(32 if pb.n[d] == 64 else 8 for d in range(3)))
+    _check(hy, pb, 20, f"sod wenoz axis {axis}")
+
+
+def test_sedov_outflow_wenoz_rk3(hy):
+    # WENO-Z's tau5 vanishes on exactly mirror-symmetric stencils, which makes
+    # the weights at the centre of an exactly symmetric blast a ratio of
+    # rounding errors; a 1e-6 density and pressure perturbation makes the problem well
+    # conditioned, so two correct implementations agree to rounding
+    pb = P.sedov(N=32, seed=7, noise=1e-6).with_(block=(16, 16, 16), recon=P.WENOZ, rk=3)
+    _check(hy, pb, 12, "sedov wenoz")
+
+
+@pytest.mark.parametrize("recon", [P.WENOZ, P.PPM4])
+def test_fofc_hypersonic_rk3(hy, recon):
+    pb = P.turbulence(N=32, seed=5, kmax=8, mach=20).with_(block=(16, 16, 16), recon=recon, rk=3,
+                                                           fofc=1)
+    U, q, ref = _check(hy, pb, 12, f"fofc rk3 {recon}")
+    assert ref["fofc_cells"] > 0
+
+
+def test_entropy_wave_fifth_order_on_gpu(hy):
+    # entropy waves are exact at any amplitude: the GPU path on its own
+    # reproduces the fifth order of WENO-Z (y-axis wave, several blocks)
+    errs = []
+    for N in (16, 32, 64):
+        pb = P.entropy_wave(N=N, amp=0.2, axis=1, ntrans=8).with_(block=(8, N // 2, 8),
+                                                                   recon=P.WENOZ, rk=3, cfl=0.05)
+        g = hy.Problem(pb).set_state()
+        while True:
+            q = g.query()
+            if q["t"] + q["dt"] > 1.0:
+                break
+            g.advance(1)
+        U = g.get_state()
+        g.close()
+        ex = P.entropy_wave(N=N, amp=0.2, axis=1, ntrans=8, t=q["t"]).U
+        errs.append(float(np.abs(U[0] - ex[0]).mean() / 0.2))
+    r = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    print(f"[entropy wave gpu] errs {errs} rates {r}", flush=True)
+    assert np.all(r >= 4.5)
+
+
+@pytest.mark.parametrize("case", ["turb_wenoz", "kh_wenoz", "sedov_wenoz"])
+def test_mixed_wenoz_rk3_vs_fp64_reference(hy, case):
+    if case == "turb_wenoz":
+        pb, steps = P.turbulence(N=48, seed=1).with_(block=(24, 24, 24)), 10
+    elif case == "kh_wenoz":
+        pb, steps = P.kelvin_helmholtz(N=48, seed=2).with_(block=(24, 24, 24)), 10
+    else:
+        # FP32 cannot resolve a 1e-6 break of the blast's mirror symmetry well
+        # enough for WENO-Z's weights (tau5 ~ 0 on near-symmetric stencils):
+        # there mixed precision departs from FP64 at the 1e-4 level; a 1e-3
+        # break keeps it at 1e-7
+        pb, steps = P.sedov(N=32, seed=3, noise=1e-3).with_(block=(16, 16, 16)), 20
+    pb = pb.with_(recon=P.WENOZ, rk=3)
+    ref = oracle.advance(pb, steps)
+    U, _ = _run(hy, pb.with_(precision=P.MIXED), steps)
+    r = _rel(U, ref["U"])
+    print(f"[mixed {case}] rel L1 vs FP64 reference {r:.3e}", flush=True)
+    assert r <= 1e-5
+
+
+def test_wenoz_rk3_every_tile_shape_bitwise(hy):
+    pb = P.turbulence(N=32, seed=9, kmax=8).with_(block=(32, 32, 32), recon=P.WENOZ, rk=3)
+    outs = [_run(hy, pb, 5, variant=v, kc=kc)[0]
+            for v in range(len(hy.variants())) for kc in (32, 7, 1)]
+    for U in outs[1:]:
+        assert np.array_equal(U, outs[0])
+
+
+@pytest.mark.parametrize("recon", [P.PLM, P.PPM4, P.WENOZ])
+@pytest.mark.parametrize("prec", [P.FP64, P.MIXED])
+def test_uniform_state_rk3(hy, recon, prec):
+    pb = P.uniform(n=(32, 24, 16), rho=1.3, v=(0.3, -0.2, 0.4), p=0.8, bc=P.PERIODIC)
+    pb = pb.with_(block=(16, 8, 8), recon=recon, precision=prec, rk=3)
+    U, q = _run(hy, pb, 3)
+    ulp = np.spacing(np.abs(pb.U))
+    assert np.all(np.abs(U - pb.U) <= 2 * 3 * 3 * ulp)
+    assert q["floor_hits"] == 0
+
+
+def test_batch_mixing_integrators_equals_alone(hy):
+    pbs = [P.turbulence(N=32, seed=21, kmax=8).with_(block=(16, 16, 16), recon=P.WENOZ, rk=3),
+           P.turbulence(N=32, seed=22, kmax=8).with_(block=(16, 16, 16), recon=P.WENOZ, rk=2),
+           P.sedov(N=32, seed=23).with_(block=(32, 32, 32), rk=3),
+           P.sedov(N=32, seed=24).with_(block=(32, 32, 32)),
+           P.kelvin_helmholtz(N=32, seed=25).with_(block=(16, 16, 16), recon=P.PPM4, rk=3,
+                                                   precision=P.MIXED)]
+    steps = [5, 7, 4, 6, 3]
+    alone = [_run(hy, pb, n) for pb, n in zip(pbs, steps)]
+    gs = [hy.Problem(pb).set_state() for pb in pbs]
+    hy.batch_advance(gs, steps)
+    for g, (U, q), n in zip(gs, alone, steps):
+        Ub, qb = g.get_state(), g.query()
+        assert np.array_equal(Ub, U) and qb["dt"] == q["dt"] and qb["t"] == q["t"]
+        assert qb["steps"] == n
+        g.close()
+
+
+def test_graph_replay_rk3(hy):
+    import torch
+    pb = P.turbulence(N=32, seed=26, kmax=8).with_(block=(16, 16, 16), recon=P.WENOZ, rk=3, fofc=1)
+    ref, _ = _run(hy, pb, 6)
+    g = hy.Problem(pb).set_state()
+    s = torch.cuda.Stream()
+    for _ in range(3):
+        hy.batch_advance_graph([g], [2], stream=s)
+        s.synchronize()
+    assert np.array_equal(g.get_state(), ref)
+    g.close()
+
+
+def test_workspace_has_third_register(hy):
+    pb = P.turbulence(N=16, seed=1, kmax=4).with_(block=(8, 8, 8))
+    n2 = hy.workspace_bytes(pb)
+    n3 = hy.workspace_bytes(pb.with_(rk=3))
+    assert n3 - n2 == (16 ** 3 * 5 * 8 + 255) // 256 * 256
+    with pytest.raises(hy.HydroError):
+        hy.workspace_bytes(pb.with_(rk=4))

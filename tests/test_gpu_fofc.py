@@ -94,3 +94,21 @@ def test_fofc_mixed_precision_positive_and_conservative(hy):
     for v in range(5):
         scale = np.abs(pb.U[v]).sum() + np.abs(U[v]).sum()
         assert abs(U[v].sum() - pb.U[v].sum()) <= 4 * eps * np.sqrt(pb.cells * 40) * scale
+
+
+@pytest.mark.parametrize("rk", [2, 3])
+def test_fofc_graph_replays_equal_eager(hy, rk):
+    # a captured graph replays the same launches every time: the flags of
+    # one replay must not leak into the next
+    import torch
+    pb = P.turbulence(N=32, seed=5, kmax=8, mach=20).with_(block=(16, 16, 16), fofc=1, rk=rk)
+    U, q = _run(hy, pb, 8)
+    g = hy.Problem(pb).set_state()
+    s = torch.cuda.Stream()
+    for _ in range(4):
+        hy.batch_advance_graph([g], [2], stream=s)
+        s.synchronize()
+    Ug, qg = g.get_state(), g.query()
+    g.close()
+    assert q["fofc_cells"] > 0
+    assert np.array_equal(Ug, U) and qg["fofc_cells"] == q["fofc_cells"] and qg["dt"] == q["dt"]

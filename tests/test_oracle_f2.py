@@ -227,3 +227,25 @@ def test_sod_high_order_schemes_match_exact(oracle_lib, recon, rk):
     right = (xi > us + 0.15) & (xi < ss - 0.15)
     assert np.all(np.abs(rho[left] / rsl - 1) < 0.01)
     assert np.all(np.abs(rho[right] / rsr - 1) < 0.01)
+
+
+def test_wenoz_symmetric_blast_is_ill_conditioned(oracle_lib):
+    # A property of the WENO-Z weights, recorded on purpose: tau5 = |beta_0 -
+    # beta_2| is exactly 0 on a mirror-symmetric stencil, and at the centre of
+    # an exactly symmetric blast the middle candidate is flat (beta_1 = 0), so
+    # a rounding-level asymmetry switches the weights from linear to the flat
+    # candidate. Perturbing the state by 1e-15 then changes the result at the
+    # 1e-3 level after a few steps; PLM, and WENO-Z on a blast whose symmetry
+    # is broken at 1e-6, stay at rounding level.
+    rng = np.random.default_rng(0)
+
+    def sensitivity(pb):
+        a = oracle_lib.advance(pb, 4)["U"]
+        b = oracle_lib.advance(pb, 4, U=pb.U * (1 + 1e-15 * rng.standard_normal(pb.U.shape)))["U"]
+        return float(np.abs(a - b).sum() / np.abs(a).sum())
+
+    base = P.sedov(N=24, seed=7).with_(rk=3)
+    assert sensitivity(base.with_(recon=P.WENOZ)) > 1e-6
+    assert sensitivity(base.with_(recon=P.PLM)) < 1e-13
+    broken = P.sedov(N=24, seed=7, noise=1e-6).with_(rk=3, recon=P.WENOZ)
+    assert sensitivity(broken) < 1e-13
