@@ -8,10 +8,20 @@ RK stages, CFL reduction). `value` is cell-updates/s in FP64 (interior cells x
 steps / wall seconds, state resident in HBM); the mixed-precision path is
 timed the same way and reported beside it.
 
-Prints one JSON line. Also:
+Prints one JSON line. Beside the headline it reports, unless switched off:
+  kh512     the 512^3 Kelvin-Helmholtz workload (64 MeshBlocks of 128^3, PPM4,
+            10 steps), FP64 and mixed
+  schemes   the 256^3 workload with WENO-Z + SSP-RK3 (FP64 and mixed) and
+            PPM4 + RK2 (FP64)
+  batch     48 Sedov problems of seeded sizes, one launch per stage for all
+  serving   a seeded Poisson stream of requests, continuous batching by HBM
+            budget against one request at a time (p50/p99 latency)
+  small_problem, cpu_baseline
+Options:
   --copy-probe BYTES   run the library's plain copy kernel on a buffer of BYTES
                        (used to calibrate rocprofv3 byte counters)
   --skip-cpu           skip the CPU reference-solver baseline
+  --headline-only      only the 256^3 FP64/mixed lines (profiling runs)
 """
 import argparse
 import hashlib
@@ -31,6 +41,10 @@ HBM_PEAK_GBS = 8000.0
 # writes V (2 x 40 B); stage 2 reads V and U and writes U (3 x 40 B)
 BYTES_STAGE = {1: 80.0, 2: 120.0}
 COUNTERS = os.path.join(ROOT, "profiles", "stage_turbulence256_counters.json")
+# FP64 vector lanes per second: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz
+# (one FP64 add, mul or fma per lane per clock; 78.6 TFLOP/s counts an fma
+# as two flops)
+FP64_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 
 
 def kernel_source_hash():
@@ -58,10 +72,14 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--launch", default="auto",
                     help="tile variant and z-chunk as V,KC (FP64 and mixed), or 'auto' to autotune")
-    ap.add_argument("--batch", action="store_true",
-                    help="also run the 48-problem Sedov batch (mixed, 50 steps)")
-    ap.add_argument("--serve", type=int, default=0, metavar="COUNT",
-                    help="also serve COUNT requests of the seeded Poisson stream")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 48-problem Sedov batch (mixed, 50 steps)")
+    ap.add_argument("--serve", type=int, default=120, metavar="COUNT",
+                    help="serve COUNT requests of the seeded Poisson stream (0: skip)")
+    ap.add_argument("--skip-kh", action="store_true", help="skip the 512^3 PPM4 workload")
+    ap.add_argument("--skip-schemes", action="store_true", help="skip WENO-Z/RK3 and PPM4 at 256^3")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the 256^3 FP64 (and mixed) lines")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     args = ap.parse_args()
 
@@ -90,8 +108,10 @@ def main():
     pb, _ = P.workload_turbulence_256(N=args.N, block=args.block)
     cells = pb.cells
 
-    def run(precision):
-        g = hy.Problem(pb.with_(precision=precision)).set_state()
+    def run(precision, prob=None, steps=None):
+        prob = pb if prob is None else prob
+        steps = args.steps if steps is None else steps
+        g = hy.Problem(prob.with_(precision=precision)).set_state()
         if args.launch == "auto":
             g.autotune_steps(2)
         else:
@@ -100,7 +120,7 @@ def main():
         g.advance(args.warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ms1, ms2 = g.advance_timed(args.steps)
+        ms1, ms2 = g.advance_timed(steps)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         q = g.query()
@@ -173,7 +193,7 @@ def main():
             "dtype": "f32 reconstruct/Riemann, f64 state/divergence/dt",
         }
 
-    if not args.skip_cpu:
+    if not args.skip_cpu and not args.headline_only:
         import oracle
         oracle.build(force=False)
         nsteps = args.cpu_steps
@@ -191,13 +211,76 @@ def main():
         }
         assert r["status"] == 0
 
-    out["small_problem"] = run_small_workload(hy, P, torch)
-    if args.batch:
-        out["batch"] = run_batch_workload(hy, P, torch)
-    if args.serve:
-        out["serving"] = run_serving_workload(hy, P, args.serve, args.serve_budget_gb)
+    valu = valu_summary(cells, a1 if dom == 1 else a2, dom)
+    if valu is not None:
+        out["roofline"]["valu"] = valu
+
+    if not args.headline_only:
+        out["small_problem"] = run_small_workload(hy, P, torch)
+        if not args.skip_schemes:
+            out["schemes"] = run_schemes(run, pb, P, args.steps)
+        if not args.skip_kh:
+            out["kh512"] = run_kh512(run, P)
+        if not args.no_batch:
+            out["batch"] = run_batch_workload(hy, P, torch)
+        if args.serve:
+            out["serving"] = run_serving_workload(hy, P, args.serve, args.serve_budget_gb)
 
     print(json.dumps(out), flush=True)
+
+
+def valu_summary(cells, avg_s, stage):
+    """FP64 vector work of the dominant stage kernel from the committed SQ
+    counters (instructions per launch, wave-level), if they were taken on the
+    current kernel source: issued FP64 lane operations per second against the
+    chip's FP64 lane rate."""
+    if not os.path.exists(COUNTERS):
+        return None
+    c = json.load(open(COUNTERS))
+    if c.get("kernel_source_hash") != kernel_source_hash() or c.get("cells") != cells:
+        return None
+    n = c.get(f"stage{stage}_fp64_valu_insts_per_launch")
+    if n is None:
+        return None
+    ops = 64.0 * n / avg_s
+    return {"fp64_lane_ops_per_s": ops, "peak": FP64_LANE_OPS_PEAK, "frac": ops / FP64_LANE_OPS_PEAK,
+            "fp64_valu_insts_per_cell": n / cells,
+            "valu_insts_per_cell": c.get(f"stage{stage}_valu_insts_per_launch", 0) / cells}
+
+
+def run_schemes(run, pb, P, steps):
+    """The 256^3 workload with the paper's higher-order options."""
+    res = {}
+    for name, kw, precs in (("wenoz_rk3", dict(recon=P.WENOZ, rk=3), (P.FP64, P.MIXED)),
+                            ("ppm4_rk2", dict(recon=P.PPM4, rk=2), (P.FP64,))):
+        for prec in precs:
+            log(f"timing {name} {'fp64' if prec == P.FP64 else 'mixed'}")
+            r = run(prec, prob=pb.with_(**kw), steps=steps)
+            res[f"{name}_{'fp64' if prec == P.FP64 else 'mixed'}"] = {
+                "value": pb.cells * steps / r["sec"], "unit": "cell-updates/s",
+                "ms_per_step": 1e3 * r["sec"] / steps, "launch": list(r["launch"])}
+    return res
+
+
+def run_kh512(run, P):
+    """512^3 periodic Kelvin-Helmholtz layer in 64 MeshBlocks of 128^3, PPM4,
+    10 steps: FP64 and mixed throughput."""
+    log("building 512^3 Kelvin-Helmholtz")
+    pb, steps = P.workload_kh_512()
+    out = {"workload": "Kelvin-Helmholtz 512^3 periodic, 64 MeshBlocks of 128^3, PPM4+HLLC, SSP-RK2, "
+                       "CFL 0.3, seed 2", "steps": steps}
+    res = {}
+    for prec in (P.FP64, P.MIXED):
+        log(f"timing kh512 {'fp64' if prec == P.FP64 else 'mixed'}")
+        res[prec] = run(prec, prob=pb, steps=steps)
+    out["fp64"] = {"value": pb.cells * steps / res[P.FP64]["sec"], "unit": "cell-updates/s",
+                   "ms_per_step": 1e3 * res[P.FP64]["sec"] / steps, "launch": list(res[P.FP64]["launch"])}
+    out["mixed"] = {"value": pb.cells * steps / res[P.MIXED]["sec"], "unit": "cell-updates/s",
+                    "ms_per_step": 1e3 * res[P.MIXED]["sec"] / steps,
+                    "launch": list(res[P.MIXED]["launch"]),
+                    "rel_l1_vs_fp64_gpu": float(np.abs(res[P.MIXED]["U"] - res[P.FP64]["U"]).sum()
+                                                / np.abs(res[P.FP64]["U"]).sum())}
+    return out
 
 
 def run_small_workload(hy, P, torch, reps=20):
