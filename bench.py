@@ -80,7 +80,8 @@ def main():
     ap.add_argument("--skip-schemes", action="store_true", help="skip WENO-Z/RK3 and PPM4 at 256^3")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the 256^3 FP64 (and mixed) lines")
-    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-budget-gb", default="16",
+                    help="HBM budget(s) in GiB for continuous batching, comma-separated")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -340,12 +341,29 @@ def run_batch_workload(hy, P, torch, count=48, seed=3):
     hy.batch_advance(gs, steps)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    ref = [g.get_state() for g in gs[:4]]
+    # the same batch captured once into a HIP graph (capture, then a timed replay)
+    s = torch.cuda.Stream()
+    for g in gs:
+        g.set_state(stream=s)
+    hy.batch_advance_graph(gs, [steps] * len(gs), stream=s)
+    s.synchronize()
+    for g in gs:
+        g.set_state(stream=s)
+    s.synchronize()
+    t0 = time.perf_counter()
+    hy.batch_advance_graph(gs, [steps] * len(gs), stream=s)
+    s.synchronize()
+    t_graph = time.perf_counter() - t0
+    same = all(np.array_equal(g.get_state(), r) for g, r in zip(gs[:4], ref))
     floors = sum(g.query()["floor_hits"] for g in gs)
     for g in gs:
         g.close()
     return {
         "value": cells * steps / t_batch,
         "unit": "cell-updates/s",
+        "graph_replay": cells * steps / t_graph,
+        "graph_equals_eager": bool(same),
         "one_by_one": cells * steps / t_one,
         "speedup": t_one / t_batch,
         "problems": count,
@@ -357,7 +375,7 @@ def run_batch_workload(hy, P, torch, count=48, seed=3):
     }
 
 
-def run_serving_workload(hy, P, count, budget_gb, seed=4, epoch=10):
+def run_serving_workload(hy, P, count, budgets_gb, seed=4, epoch=10):
     """Poisson stream of Sod / KH / Sedov requests (32^3..256^3, 10..200
     steps, FP64 or mixed), admitted by an HBM budget: continuous batching
     against one request at a time. Initial states are generated before the
@@ -373,26 +391,25 @@ def run_serving_workload(hy, P, count, budget_gb, seed=4, epoch=10):
     mean_service = (time.perf_counter() - t0) / calib
     rate = 0.8 / mean_service
     log(f"serving: mean one-at-a-time service {mean_service * 1e3:.1f} ms -> rate {rate:.1f}/s")
-    budget = int(budget_gb * 2 ** 30)
     fifo = serve.run_fifo(serve.make_stream(seed, count, rate, inputs=inputs), keep="digest",
                           client_threads=16)
     sf = serve.summarize(fifo)
-    srv = serve.Server(budget_bytes=budget, epoch_steps=epoch, keep="digest", client_threads=16)
-    cont = srv.run(serve.make_stream(seed, count, rate, inputs=inputs))
-    sc = serve.summarize(cont)
-    same = all(a.digest == b.digest for a, b in zip(cont, fifo))
-    return {
-        "requests": count,
-        "rate_per_s": rate,
-        "mean_service_ms_one_at_a_time": mean_service * 1e3,
-        "budget_gb": budget_gb,
-        "epoch_steps": epoch,
-        "continuous": sc,
-        "fifo": sf,
-        "peak_resident_gb": srv.peak_bytes / 2 ** 30,
-        "epochs": srv.epochs,
-        "results_equal_alone": bool(same),
-    }
+    budgets = [float(b) for b in str(budgets_gb).split(",")]
+    runs = []
+    for budget_gb in budgets:
+        log(f"serving: continuous batching, budget {budget_gb} GiB")
+        srv = serve.Server(budget_bytes=int(budget_gb * 2 ** 30), epoch_steps=epoch, keep="digest",
+                           client_threads=16)
+        cont = srv.run(serve.make_stream(seed, count, rate, inputs=inputs))
+        runs.append({"budget_gb": budget_gb, "continuous": serve.summarize(cont),
+                     "peak_resident_gb": srv.peak_bytes / 2 ** 30, "epochs": srv.epochs,
+                     "results_equal_alone": bool(all(a.digest == b.digest for a, b in zip(cont, fifo)))})
+    out = {"requests": count, "rate_per_s": rate, "mean_service_ms_one_at_a_time": mean_service * 1e3,
+           "epoch_steps": epoch, "fifo": sf}
+    out.update(runs[0])
+    if len(runs) > 1:
+        out["budget_sweep"] = runs
+    return out
 
 
 if __name__ == "__main__":

@@ -49,6 +49,15 @@ __device__ __forceinline__ double rcp(double x) {
 }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Reciprocal for limiter and weight arithmetic, where a few ulps do not
+// matter: FP64 takes one Newton-Raphson step (the estimate's ~3e-8 relative
+// error squared, i.e. within ~8 ulp); FP32 the native instruction.
+__device__ __forceinline__ double rcp_lim(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float rcp_lim(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Square root. FP64: the hardware reciprocal-square-root estimate, one
 // Goldschmidt step (g ~ sqrt(x), h ~ 1/(2 sqrt(x)); the error is squared) and
 // a final Newton correction of g (squared again), which lands within an ulp;
@@ -76,13 +85,14 @@ __device__ __forceinline__ int xcd_remap(int w, int G) {
 }
 
 // ---------------------------------------------------------- reconstruction
-// PLM: van Leer harmonic-mean slope of a cell from its neighbours (faces are
-// w0 -/+ slope/2).
+// PLM: half the van Leer harmonic-mean slope of a cell from its neighbours,
+// dl dr / (dl + dr) when dl dr > 0 (faces are w0 -/+ this; halving the
+// slope 2 dl dr / (dl + dr) is exact, so nothing else changes).
 template <typename T>
-__device__ __forceinline__ T plm_slope(T wm, T w0, T wp) {
+__device__ __forceinline__ T plm_half_slope(T wm, T w0, T wp) {
   const T dl = w0 - wm, dr = wp - w0;
   const T prod = dl * dr;
-  const T s = (T(2) * prod) * rcp(dl + dr);
+  const T s = prod * rcp_lim(dl + dr);
   return prod > T(0) ? s : T(0);
 }
 
@@ -148,15 +158,15 @@ template <typename T>
 __device__ __forceinline__ T weno_mix(T wc, T q0, T q1, T q2, T b0, T b1, T b2) {
   const T eps = T(1e-36), cap = T(1e15);
   const T tau = fabs(b0 - b2);
-  const T r0 = fmin(tau * rcp(b0 + eps), cap);
-  const T r1 = fmin(tau * rcp(b1 + eps), cap);
-  const T r2 = fmin(tau * rcp(b2 + eps), cap);
+  const T r0 = fmin(tau * rcp_lim(b0 + eps), cap);
+  const T r1 = fmin(tau * rcp_lim(b1 + eps), cap);
+  const T r2 = fmin(tau * rcp_lim(b2 + eps), cap);
   const T a0 = T(0.1) * (T(1) + r0 * r0);
   const T a1 = T(0.6) * (T(1) + r1 * r1);
   const T a2 = T(0.3) * (T(1) + r2 * r2);
   // normalise the weights first: a_k can reach 1e30, which must not meet a
   // large candidate in FP32
-  const T id = rcp((a0 + a1) + a2);
+  const T id = rcp_lim((a0 + a1) + a2);
   const T mix = ((a0 * id) * q0 + (a1 * id) * q1) + (a2 * id) * q2;
   return wc + mix * T(1.0 / 6.0);
 }
@@ -381,7 +391,7 @@ struct ZQueue;
 template <typename T>
 struct ZQueue<0, T> {       // PLM
   T w0[5], w1[5];           // primitives at k and k+1
-  T s0[5];                  // limited slope at k
+  T s0[5];                  // half the limited slope at k
   double fm[5];             // z-flux through the face k-1/2
 };
 
@@ -426,8 +436,8 @@ __device__ __forceinline__ void face_flux(const Gas<T>& gas, const T* __restrict
     const T* s = sW + v * PLANE + base;
     if constexpr (RECON == 0) {
       const T c0 = s[-2 * STR], c1 = s[-STR], c2 = s[0], c3 = s[STR];
-      wl[v] = c1 + T(0.5) * plm_slope(c0, c1, c2);
-      wr[v] = c2 - T(0.5) * plm_slope(c1, c2, c3);
+      wl[v] = c1 + plm_half_slope(c0, c1, c2);
+      wr[v] = c2 - plm_half_slope(c1, c2, c3);
     } else if constexpr (RECON == 2) {
       const T c0 = s[-3 * STR], c1 = s[-2 * STR], c2 = s[-STR];
       const T c3 = s[0], c4 = s[STR], c5 = s[2 * STR];
@@ -570,10 +580,10 @@ k_stage(const StageArgs a) {
         T wl[5], wr[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-          const T sb = plm_slope(wa[v], wb[v], wc[v]);
-          const T sc = plm_slope(wb[v], wc[v], wd[v]);
-          wl[v] = wb[v] + T(0.5) * sb;
-          wr[v] = wc[v] - T(0.5) * sc;
+          const T sb = plm_half_slope(wa[v], wb[v], wc[v]);
+          const T sc = plm_half_slope(wb[v], wc[v], wd[v]);
+          wl[v] = wb[v] + sb;
+          wr[v] = wc[v] - sc;
           zq.w0[v] = wc[v];
           zq.w1[v] = wd[v];
           zq.s0[v] = sc;
@@ -710,9 +720,9 @@ k_stage(const StageArgs a) {
           T wl[5], wr[5], s1[5];
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            s1[v] = plm_slope(zq.w0[v], zq.w1[v], w2[v]);
-            wl[v] = zq.w0[v] + T(0.5) * zq.s0[v];
-            wr[v] = zq.w1[v] - T(0.5) * s1[v];
+            s1[v] = plm_half_slope(zq.w0[v], zq.w1[v], w2[v]);
+            wl[v] = zq.w0[v] + zq.s0[v];
+            wr[v] = zq.w1[v] - s1[v];
           }
           zflux(gas, wl, wr, fz);
 #pragma unroll
@@ -868,8 +878,8 @@ __device__ void face_pair(const Geo& geo, const Floors& fl, const Gas<T>& gas,
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     if constexpr (RECON == 0) {
-      wl[v] = c[1][v] + T(0.5) * plm_slope(c[0][v], c[1][v], c[2][v]);
-      wr[v] = c[2][v] - T(0.5) * plm_slope(c[1][v], c[2][v], c[3][v]);
+      wl[v] = c[1][v] + plm_half_slope(c[0][v], c[1][v], c[2][v]);
+      wr[v] = c[2][v] - plm_half_slope(c[1][v], c[2][v], c[3][v]);
     } else if constexpr (RECON == 2) {
       wl[v] = weno_right(c[0][v], c[1][v], c[2][v], c[3][v], c[4][v]);
       wr[v] = weno_right(c[5][v], c[4][v], c[3][v], c[2][v], c[1][v]);
