@@ -66,6 +66,8 @@ def _bind(L):
     L.or_ppm4_cell.restype = None
     L.or_wenoz_cell.argtypes = [dp, dp, dp]
     L.or_wenoz_cell.restype = None
+    L.or_ppmx_cell.argtypes = [dp, dp, dp]
+    L.or_ppmx_cell.restype = None
     L.or_hllc.argtypes = [ctypes.c_double, dp, dp, dp]
     L.or_hllc.restype = None
     L.or_llf.argtypes = [ctypes.c_double, dp, dp, dp]
@@ -194,6 +196,12 @@ class Oracle:
         self._L.or_ppm4_cell(_dp(w), ctypes.byref(l), ctypes.byref(r))
         return l.value, r.value
 
+    def ppmx_cell(self, w5):
+        w = np.ascontiguousarray(w5, dtype=np.float64)
+        l, r = ctypes.c_double(), ctypes.c_double()
+        self._L.or_ppmx_cell(_dp(w), ctypes.byref(l), ctypes.byref(r))
+        return l.value, r.value
+
     def wenoz_cell(self, w5):
         w = np.ascontiguousarray(w5, dtype=np.float64)
         l, r = ctypes.c_double(), ctypes.c_double()
@@ -261,6 +269,10 @@ def plm_cell(wm, w0, wp):
 
 def ppm4_cell(w5):
     return _inst().ppm4_cell(w5)
+
+
+def ppmx_cell(w5):
+    return _inst().ppmx_cell(w5)
 
 
 def wenoz_cell(w5):

@@ -11,7 +11,7 @@
  * advance"):
  *   ghost-zone fill (Sec. 2, boundary conditions)
  *   -> conserved to primitive, W = [rho, v, u_g], p = (gamma-1) u_g (Sec. 3.1, Eq. 4)
- *   -> reconstruction on primitives, PLM, PPM4 or WENO-Z (Sec. 3)
+ *   -> reconstruction on primitives, PLM, PPM4, PPMX or WENO-Z (Sec. 3)
  *   -> HLLC Riemann fluxes in x, y and z (Sec. 3; Toro's textbook, Ch. 10)
  *   -> flux divergence and a low-storage SSP-RK stage (Sec. 3, method of lines;
  *      one, two or three stages)
@@ -44,14 +44,14 @@
 #endif
 
 enum { OR_PERIODIC = 0, OR_OUTFLOW = 1 };
-enum { OR_PLM = 0, OR_PPM4 = 1, OR_WENOZ = 2 };
+enum { OR_PLM = 0, OR_PPM4 = 1, OR_WENOZ = 2, OR_PPMX = 3 };
 enum { OR_OK = 0, OR_ERR_ARG = 1, OR_ERR_NOMEM = 2, OR_ERR_STATE = 4 };
 
 /* Problem description passed from Python (ctypes mirror in oracle/__init__.py). */
 typedef struct {
   int32_t n[3];      /* interior cells nx, ny, nz                      */
   int32_t bc[3][2];  /* per axis (lower, upper): OR_PERIODIC/OR_OUTFLOW */
-  int32_t recon;     /* OR_PLM (2 ghosts), OR_PPM4 or OR_WENOZ (3)     */
+  int32_t recon;     /* OR_PLM (2 ghosts), OR_PPM4/WENOZ/PPMX (3)      */
   int32_t fofc;      /* 1: first-order flux correction in every stage  */
   int32_t rk;        /* stages of the SSP-RK integrator: 1, 2 or 3     */
   double dx[3];      /* cell widths                                    */
@@ -272,6 +272,71 @@ void or_wenoz_cell(const double w[5], double* left, double* right) {
 }
 
 /* ------------------------------------------------------------------------
+ * PPMX: PPM with the extremum-preserving limiters of Colella & Sekora (2008)
+ * as used by McCorquodale & Colella (Sec. 3 names them, without formulas).
+ * A limited second difference keeps the sign of all its arguments and the
+ * smallest magnitude among them, the neighbouring second differences
+ * weighted by C = 1.25; it is 0 if the signs differ.
+ *  1. Fourth-order interface value between b and c (neighbours a, d):
+ *     7/12 (b + c) - 1/12 (a + d).
+ *  2. If that value f lies outside [b, c], it is replaced by
+ *     (b + c)/2 - D/6, D the limited second difference of 3 (b - 2f + c),
+ *     with neighbours a - 2b + c and b - 2c + d.
+ *  3. Cell w_i with edges aL, aR, dm = w_i - aL, dp = aR - w_i. At an
+ *     extremum (dm dp <= 0, or the cell average itself is a local extremum)
+ *     the parabola's curvature 6 (aL + aR - 2 w_i) is limited against the
+ *     centred and the two one-sided second differences of the cell averages,
+ *     and both edge offsets are scaled by limited / unlimited curvature (0 if
+ *     the curvature is 0). Elsewhere the usual PPM overshoot test applies:
+ *     an edge offset larger than twice the other is cut to twice it.
+ * ---------------------------------------------------------------------- */
+#define OR_PPMX_C 1.25
+
+static double lim2(int n, const double* x) {
+  /* x[0] is the second difference to limit; x[1..n-1] its neighbours */
+  int pos = 1, neg = 1;
+  for (int q = 0; q < n; ++q) {
+    pos &= x[q] > 0.0;
+    neg &= x[q] < 0.0;
+  }
+  if (!pos && !neg) return 0.0;
+  double m = fabs(x[0]);
+  for (int q = 1; q < n; ++q)
+    if (OR_PPMX_C * fabs(x[q]) < m) m = OR_PPMX_C * fabs(x[q]);
+  return pos ? m : -m;
+}
+
+/* limited interface value between b and c, neighbours a and d */
+static double ppmx_interface(double a, double b, double c, double d) {
+  double f = 7.0 / 12.0 * (b + c) - 1.0 / 12.0 * (a + d);
+  if ((f - b) * (c - f) < 0.0) {
+    const double x[3] = {3.0 * (b - 2.0 * f + c), a - 2.0 * b + c, b - 2.0 * c + d};
+    f = 0.5 * (b + c) - lim2(3, x) / 6.0;
+  }
+  return f;
+}
+
+/* PPMX face values of cell c from w[0..4] = cells c-2..c+2 */
+void or_ppmx_cell(const double w[5], double* left, double* right) {
+  double aL = ppmx_interface(w[0], w[1], w[2], w[3]);
+  double aR = ppmx_interface(w[1], w[2], w[3], w[4]);
+  const double a = w[2];
+  const double dm = a - aL, dp = aR - a;
+  if (dm * dp <= 0.0 || (w[3] - a) * (a - w[1]) <= 0.0) {
+    const double d2 = 6.0 * (aL + aR - 2.0 * a);
+    const double x[4] = {d2, w[1] - 2.0 * a + w[3], w[0] - 2.0 * w[1] + a, a - 2.0 * w[3] + w[4]};
+    const double ratio = d2 != 0.0 ? lim2(4, x) / d2 : 0.0;
+    aL = a - ratio * dm;
+    aR = a + ratio * dp;
+  } else {
+    if (fabs(dp) >= 2.0 * fabs(dm)) aR = a + 2.0 * dm;
+    if (fabs(dm) >= 2.0 * fabs(dp)) aL = a - 2.0 * dp;
+  }
+  *left = aL;
+  *right = aR;
+}
+
+/* ------------------------------------------------------------------------
  * HLLC Riemann solver (Sec. 3 names HLLC; the Toro-Spruce-Speares solver of
  * Toro's textbook Ch. 10 with PVRS pressure-based wave-speed estimates).
  * States are primitive [rho, u_n, u_t1, u_t2, p]; the flux is
@@ -416,6 +481,9 @@ static void face_states(const or_params* p, const work* w, int d, int i, int j, 
       if (p->recon == OR_PPM4) {
         or_ppm4_cell(&s[0], &l0, &r0); /* cell c-1: cells c-3..c+1 */
         or_ppm4_cell(&s[1], &l1, &r1); /* cell c:   cells c-2..c+2 */
+      } else if (p->recon == OR_PPMX) {
+        or_ppmx_cell(&s[0], &l0, &r0);
+        or_ppmx_cell(&s[1], &l1, &r1);
       } else {
         or_wenoz_cell(&s[0], &l0, &r0);
         or_wenoz_cell(&s[1], &l1, &r1);
@@ -662,7 +730,7 @@ int or_advance(const or_params* p, double* U, int nsteps, double* t, double* dt,
     if (p->n[d] < 1) return OR_ERR_ARG;
     if ((p->bc[d][0] == OR_PERIODIC) != (p->bc[d][1] == OR_PERIODIC)) return OR_ERR_ARG;
   }
-  if (p->rk < 1 || p->rk > 3 || p->recon < OR_PLM || p->recon > OR_WENOZ) return OR_ERR_ARG;
+  if (p->rk < 1 || p->rk > 3 || p->recon < OR_PLM || p->recon > OR_PPMX) return OR_ERR_ARG;
   work w;
   if (work_alloc(&w, p) != OR_OK) { work_free(&w); return OR_ERR_NOMEM; }
   const size_t nt = 5 * ncell(p);

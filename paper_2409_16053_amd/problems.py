@@ -28,13 +28,14 @@ OUTFLOW = 1
 PLM = 0
 PPM4 = 1
 WENOZ = 2
+PPMX = 3
 FP64 = 0
 MIXED = 1
 
 # Ghost depth each reconstruction needs: PLM reads c-1..c+1 of a cell, so a face
-# needs two cells on each side; PPM4 (Colella & Woodward 1984) and WENO-Z
+# needs two cells on each side; PPM4 (Colella & Woodward 1984), PPMX and WENO-Z
 # (c-2..c+2 of a cell) need three.
-NGHOST = {PLM: 2, PPM4: 3, WENOZ: 3}
+NGHOST = {PLM: 2, PPM4: 3, WENOZ: 3, PPMX: 3}
 
 
 @dataclass

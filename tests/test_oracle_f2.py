@@ -1,5 +1,5 @@
-"""Pins of the higher-order options of the CPU reference solver: WENO-Z
-reconstruction and the one- and three-stage SSP-RK integrators (Sec. 3).
+"""Pins of the higher-order options of the CPU reference solver: WENO-Z and
+PPMX reconstruction and the one- and three-stage SSP-RK integrators (Sec. 3).
 
 * WENO-Z face values are exact for cell averages of quadratics (each
   third-order candidate is), converge at fifth order on smooth data, and take
@@ -10,8 +10,12 @@ reconstruction and the one- and three-stage SSP-RK integrators (Sec. 3).
   paper reports for its extremum-preserving schemes (at least fourth), PPM4
   at second order; at fixed resolution the error falls with the time step at
   third order for RK3, second for RK2 and first for RK1.
+* PPMX keeps the exact edges of a smooth extremum (PPM4 clips it), adds no
+  new extremum at a jump, and converges at fourth order on entropy waves, as
+  the paper reports for it.
 * Shu & Osher's shock-entropy interaction (the paper's Fig. 2): at 200 cells
-  WENO-Z + RK3 resolves the post-shock entropy waves better than PLM + RK2.
+  WENO-Z + RK3 (and PPMX + RK3) resolve the post-shock entropy waves better
+  than PLM + RK2.
 """
 import numpy as np
 import pytest
@@ -108,6 +112,76 @@ def test_wenoz_mirror_and_constant(oracle_lib):
     assert oracle_lib.wenoz_cell([0.7] * 5) == (0.7, 0.7)
 
 
+# ------------------------------------------------------------ PPMX units
+def test_ppmx_keeps_a_smooth_extremum(oracle_lib):
+    # averages of 1 - x^2 over cells of width h centred at -2h..2h: the
+    # fourth-order interfaces are exact and the extremum limiter leaves them,
+    # so both edges of the peak cell are the parabola's values at +-h/2;
+    # PPM4's monotonicity constraint flattens the same cell
+    for h in (0.1, 0.37):
+        c = (1.0, 0.0, -1.0)
+        w = [_avg_poly(c, (m - 0.5) * h, (m + 0.5) * h) for m in range(-2, 3)]
+        left, right = oracle_lib.ppmx_cell(w)
+        exact = 1.0 - 0.25 * h * h
+        assert abs(left - exact) <= 1e-14 and abs(right - exact) <= 1e-14
+        l4, r4 = oracle_lib.ppm4_cell(w)
+        assert l4 == r4 == w[2]
+
+
+def test_ppmx_exact_for_monotone_cubics(oracle_lib):
+    # away from extrema and overshoots the edges are the fourth-order
+    # interface values, exact for averages of cubics
+    rng = np.random.default_rng(24)
+    checked = 0
+    for _ in range(200):
+        c = rng.normal(size=4)
+        h = 10.0 ** rng.uniform(-2, -0.5)
+        x0 = rng.uniform(-1, 1)
+        p = lambda x: c[0] + c[1] * x + c[2] * x * x + c[3] * x ** 3
+        dp = lambda x: c[1] + 2 * c[2] * x + 3 * c[3] * x * x
+        if min(abs(dp(x0 + t * h)) for t in np.linspace(-2.5, 2.5, 11)) < 0.3 * abs(dp(x0)) + 1e-3:
+            continue  # keep the stencil strictly monotone
+        w = [_avg_poly(c, x0 + (m - 0.5) * h, x0 + (m + 0.5) * h) for m in range(-2, 3)]
+        eL, eR = p(x0 - 0.5 * h), p(x0 + 0.5 * h)
+        em, ep = w[2] - eL, eR - w[2]
+        if abs(ep) >= 1.9 * abs(em) or abs(em) >= 1.9 * abs(ep):
+            continue  # the exact parabola would overshoot: the limiter is meant to act
+        left, right = oracle_lib.ppmx_cell(w)
+        scale = max(abs(v) for v in w) + 1.0
+        assert abs(left - p(x0 - 0.5 * h)) <= 1e-12 * scale
+        assert abs(right - p(x0 + 0.5 * h)) <= 1e-12 * scale
+        checked += 1
+    assert checked > 50
+
+
+def test_ppmx_parabola_monotone_on_monotone_data(oracle_lib):
+    # on strictly monotone averages the cell's parabola (edges aL, aR,
+    # average a) must not turn inside the cell: |a6| <= |aR - aL| with
+    # a6 = 6 (a - (aL + aR)/2) (the PPM monotonicity condition)
+    rng = np.random.default_rng(26)
+    for _ in range(500):
+        w = np.sort(rng.uniform(-1, 1, size=5) * 10.0 ** rng.uniform(-2, 2))
+        if rng.uniform() < 0.5:
+            w = w[::-1].copy()
+        if np.any(np.diff(w) == 0.0):
+            continue
+        left, right = oracle_lib.ppmx_cell(w)
+        a6 = 6.0 * (w[2] - 0.5 * (left + right))
+        assert abs(a6) <= abs(right - left) * (1 + 1e-12) + 1e-14 * np.abs(w).max()
+
+
+def test_ppmx_no_new_extremum_at_a_jump(oracle_lib):
+    rng = np.random.default_rng(25)
+    for _ in range(100):
+        lo_, hi_ = sorted(rng.normal(size=2) * 10)
+        k = int(rng.integers(1, 5))
+        w = np.array([lo_] * k + [hi_] * (5 - k))
+        w = w + 1e-3 * (hi_ - lo_) * np.sort(rng.uniform(size=5))  # a little monotone slope
+        left, right = oracle_lib.ppmx_cell(w)
+        for e in (left, right):
+            assert w[1] - 1e-12 <= e <= w[3] + 1e-12 or min(w[1:4]) - 1e-12 <= e <= max(w[1:4]) + 1e-12
+
+
 # ------------------------------------------------------------ entropy waves
 def _run_to(oracle_lib, pb, t_end, max_steps=50000):
     U, t, dt = pb.U, 0.0, oracle_lib.new_dt(pb, pb.U)
@@ -140,6 +214,12 @@ def test_entropy_wave_wenoz_rk3_high_order(oracle_lib, axis):
     assert np.all(r >= 4.5), (errs, r)
 
 
+def test_entropy_wave_ppmx_rk3_fourth_order(oracle_lib):
+    errs = [_entropy_error(oracle_lib, N, P.PPMX, 3, 0.3) for N in (16, 32, 64)]
+    r = _rates(errs)
+    assert np.all((r >= 3.8) & (r <= 4.3)), (errs, r)
+
+
 def test_entropy_wave_ppm4_rk3_second_order(oracle_lib):
     errs = [_entropy_error(oracle_lib, N, P.PPM4, 3, 0.05) for N in (16, 32, 64)]
     r = _rates(errs)
@@ -157,7 +237,7 @@ def test_time_order_of_the_integrators(oracle_lib, recon, rk, N, cfls, lo_, hi_)
     assert lo_ <= r <= hi_, (errs, r)
 
 
-@pytest.mark.parametrize("recon", [P.PLM, P.PPM4, P.WENOZ])
+@pytest.mark.parametrize("recon", [P.PLM, P.PPM4, P.WENOZ, P.PPMX])
 @pytest.mark.parametrize("rk", [1, 2, 3])
 def test_uniform_state_preserved(oracle_lib, recon, rk):
     # Every face sees the same two states, so L(U) = 0 exactly. RK1 and RK2
@@ -175,7 +255,7 @@ def test_uniform_state_preserved(oracle_lib, recon, rk):
             assert np.all(np.abs(r["U"] - pb.U) <= 2 * rk * steps * ulp)
 
 
-@pytest.mark.parametrize("recon,rk", [(P.WENOZ, 3), (P.WENOZ, 2), (P.PPM4, 3), (P.PLM, 1)])
+@pytest.mark.parametrize("recon,rk", [(P.WENOZ, 3), (P.WENOZ, 2), (P.PPM4, 3), (P.PLM, 1), (P.PPMX, 3)])
 def test_periodic_conservation_all_schemes(oracle_lib, recon, rk):
     pb = P.turbulence(N=16, seed=31, kmax=5).with_(recon=recon, rk=rk)
     steps = 4
@@ -198,15 +278,17 @@ def test_shu_osher_wenoz_resolves_entropy_waves(oracle_lib):
     x = -5.0 + (np.arange(200) + 0.5) * 0.05
     win = (x > 0.5) & (x < 2.2)  # the post-shock entropy waves, shock excluded
     res = {}
-    for recon, rk in ((P.WENOZ, 3), (P.PLM, 2)):
+    for recon, rk in ((P.WENOZ, 3), (P.PLM, 2), (P.PPMX, 3)):
         rho = _run_to(oracle_lib, P.shu_osher(N=200).with_(recon=recon, rk=rk), t_end)[0, 0, 0]
         res[recon] = (np.abs(rho - rho_ref)[win].mean(), np.ptp(rho[win]))
     assert res[P.WENOZ][0] <= 0.9 * res[P.PLM][0], res
     assert res[P.WENOZ][1] >= 1.2 * res[P.PLM][1], res
+    assert res[P.PPMX][0] <= 0.93 * res[P.PLM][0], res
+    assert res[P.PPMX][1] >= 1.1 * res[P.PLM][1], res
 
 
 # ------------------------------------------------------------ Sod, exact solution
-@pytest.mark.parametrize("recon,rk", [(P.WENOZ, 3), (P.PPM4, 3)])
+@pytest.mark.parametrize("recon,rk", [(P.WENOZ, 3), (P.PPM4, 3), (P.PPMX, 3)])
 def test_sod_high_order_schemes_match_exact(oracle_lib, recon, rk):
     import exact
     gamma = 1.4

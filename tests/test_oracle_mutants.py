@@ -46,6 +46,11 @@ MUTANTS = [
     ("wenoz_indicator_index", "0.25 * (w[1] - w[3]) * (w[1] - w[3])", "0.25 * (w[1] - w[2]) * (w[1] - w[2])"),
     ("wenoz_left_not_mirrored", "const double m[5] = {w[4], w[3], w[2], w[1], w[0]};",
      "const double m[5] = {w[0], w[1], w[2], w[3], w[4]};"),
+    ("ppmx_second_order_interface", "7.0 / 12.0 * (b + c) - 1.0 / 12.0 * (a + d)",
+     "0.5 * (b + c) + 0.0 * (a + d)"),
+    ("ppmx_ratio_sign", "aL = a - ratio * dm;", "aL = a + ratio * dm;"),
+    ("ppmx_overshoot_factor", "aR = a + 2.0 * dm;", "aR = a + 3.0 * dm;"),
+    ("ppmx_limiter_constant", "#define OR_PPMX_C 1.25", "#define OR_PPMX_C 0.75"),
     ("ghost_periodic_offset", "return bchi == OR_PERIODIC ? c % n : n - 1;",
      "return bchi == OR_PERIODIC ? (c + 1) % n : n - 1;"),
     ("ghost_outflow_index", "return bclo == OR_PERIODIC ? ((c % n) + n) % n : 0;",
@@ -97,6 +102,10 @@ def _fast_pins(O):
     yield lambda: f2.test_wenoz_matches_its_definition(O)
     yield lambda: f2.test_wenoz_fifth_order_on_smooth_data(O)
     yield lambda: f2.test_wenoz_takes_the_smooth_side_of_a_jump(O)
+    yield lambda: f2.test_ppmx_keeps_a_smooth_extremum(O)
+    yield lambda: f2.test_ppmx_exact_for_monotone_cubics(O)
+    yield lambda: f2.test_ppmx_no_new_extremum_at_a_jump(O)
+    yield lambda: f2.test_ppmx_parabola_monotone_on_monotone_data(O)
     yield lambda: f2.test_time_order_of_the_integrators(O, P.WENOZ, 3, 256, (0.8, 0.4), 2.75, 3.3)
 
 
