@@ -11,8 +11,8 @@ timed the same way and reported beside it.
 Prints one JSON line. Beside the headline it reports, unless switched off:
   kh512     the 512^3 Kelvin-Helmholtz workload (64 MeshBlocks of 128^3, PPM4,
             10 steps), FP64 and mixed
-  schemes   the 256^3 workload with WENO-Z + SSP-RK3 (FP64 and mixed) and
-            PPM4 + RK2 (FP64)
+  schemes   the 256^3 workload with WENO-Z + SSP-RK3 and PPMX + SSP-RK3 (FP64
+            and mixed) and PPM4 + RK2 (FP64)
   batch     48 Sedov problems of seeded sizes, one launch per stage for all
   serving   a seeded Poisson stream of requests, continuous batching by HBM
             budget against one request at a time (p50/p99 latency)
@@ -253,6 +253,7 @@ def run_schemes(run, pb, P, steps):
     """The 256^3 workload with the paper's higher-order options."""
     res = {}
     for name, kw, precs in (("wenoz_rk3", dict(recon=P.WENOZ, rk=3), (P.FP64, P.MIXED)),
+                            ("ppmx_rk3", dict(recon=P.PPMX, rk=3), (P.FP64, P.MIXED)),
                             ("ppm4_rk2", dict(recon=P.PPM4, rk=2), (P.FP64,))):
         for prec in precs:
             log(f"timing {name} {'fp64' if prec == P.FP64 else 'mixed'}")

@@ -9,8 +9,8 @@
  * equal MeshBlocks that are processed together as one MeshBlockPack
  * (Sec. 2, "MeshBlockPacks"; "Data locality"). Each step runs the paper's
  * reconstruct-solve-advance sequence (Sec. 3): ghost zones (Sec. 2,
- * "Boundary conditions"), cons-to-prim, PLM, PPM4 or WENO-Z reconstruction
- * on primitives, HLLC fluxes in x, y and z, flux divergence and a two- or
+ * "Boundary conditions"), cons-to-prim, PLM, PPM4, PPMX or WENO-Z
+ * reconstruction on primitives, HLLC fluxes in x, y and z, flux divergence and a two- or
  * three-stage low-storage SSP Runge-Kutta update (method of lines), then the
  * CFL time step of Sec. 3, Eq. 3 taken as a minimum over all cells and
  * dimensions.
@@ -51,13 +51,13 @@ typedef enum {
 } hy_status;
 
 enum { HY_BC_PERIODIC = 0, HY_BC_OUTFLOW = 1 };
-enum { HY_PLM = 0, HY_PPM4 = 1, HY_WENOZ = 2 };
+enum { HY_PLM = 0, HY_PPM4 = 1, HY_WENOZ = 2, HY_PPMX = 3 };
 enum { HY_FP64 = 0, HY_MIXED = 1 };
 
 /* Problem definition (Sec. 2 mesh and boundaries; Sec. 3 algorithms).
  *  n[3]        global interior cells (nx, ny, nz), each >= 1.
  *  block[3]    MeshBlock interior size; must divide n and be >= the ghost
- *              depth (2 for PLM, 3 for PPM4 and WENO-Z).
+ *              depth (2 for PLM, 3 for PPM4, PPMX and WENO-Z).
  *  lo[3],hi[3] domain extents; dx_d = (hi_d - lo_d) / n_d > 0.
  *  bc[3][2]    lower/upper boundary per axis: HY_BC_PERIODIC (both sides of
  *              an axis must then be periodic) or HY_BC_OUTFLOW (zero-gradient
@@ -67,8 +67,10 @@ enum { HY_FP64 = 0, HY_MIXED = 1 };
  *              Woodward 1984 limiters) or HY_WENOZ (fifth-order WENO-Z:
  *              Jiang-Shu smoothness indicators, weights
  *              d_k (1 + (tau5 / (beta_k + 1e-36))^2) with the ratio capped at
- *              1e15, linear weights 1/10, 6/10, 3/10), all on primitive
- *              variables.
+ *              1e15, linear weights 1/10, 6/10, 3/10) or HY_PPMX (PPM
+ *              with the extremum-preserving limiters of Colella & Sekora:
+ *              fourth-order interface values, limited second differences
+ *              with C = 1.25), all on primitive variables.
  *  precision   HY_FP64 (all arithmetic in FP64) or HY_MIXED (reconstruction
  *              and the Riemann solve in FP32; cons-to-prim, flux divergence,
  *              the RK accumulation and the time step in FP64; U stays FP64).

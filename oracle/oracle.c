@@ -278,7 +278,7 @@ void or_wenoz_cell(const double w[5], double* left, double* right) {
  * smallest magnitude among them, the neighbouring second differences
  * weighted by C = 1.25; it is 0 if the signs differ.
  *  1. Fourth-order interface value between b and c (neighbours a, d):
- *     7/12 (b + c) - 1/12 (a + d).
+ *     7/12 (b + c) - 1/12 (a + d), evaluated in differences.
  *  2. If that value f lies outside [b, c], it is replaced by
  *     (b + c)/2 - D/6, D the limited second difference of 3 (b - 2f + c),
  *     with neighbours a - 2b + c and b - 2c + d.
@@ -306,9 +306,13 @@ static double lim2(int n, const double* x) {
   return pos ? m : -m;
 }
 
-/* limited interface value between b and c, neighbours a and d */
+/* limited interface value between b and c, neighbours a and d; the
+ * fourth-order value 7/12 (b + c) - 1/12 (a + d) is written as
+ * (b + c)/2 - ((a - b) + (d - c))/12 so that a constant state is reproduced
+ * exactly (otherwise rounding puts f just outside [b, b] and the limiter's
+ * branch is decided by rounding) */
 static double ppmx_interface(double a, double b, double c, double d) {
-  double f = 7.0 / 12.0 * (b + c) - 1.0 / 12.0 * (a + d);
+  double f = 0.5 * (b + c) - ((a - b) + (d - c)) / 12.0;
   if ((f - b) * (c - f) < 0.0) {
     const double x[3] = {3.0 * (b - 2.0 * f + c), a - 2.0 * b + c, b - 2.0 * c + d};
     f = 0.5 * (b + c) - lim2(3, x) / 6.0;

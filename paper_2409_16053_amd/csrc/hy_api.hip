@@ -63,8 +63,8 @@ int stages_of(const hy_config* c) { return c->rk == 3 ? 3 : 2; }
 
 bool validate(const hy_config* c, std::string& msg) {
   if (!c) { msg = "config is NULL"; return false; }
-  if (c->recon != HY_PLM && c->recon != HY_PPM4 && c->recon != HY_WENOZ) {
-    msg = "recon must be HY_PLM, HY_PPM4 or HY_WENOZ";
+  if (c->recon != HY_PLM && c->recon != HY_PPM4 && c->recon != HY_WENOZ && c->recon != HY_PPMX) {
+    msg = "recon must be HY_PLM, HY_PPM4, HY_WENOZ or HY_PPMX";
     return false;
   }
   if (c->rk != 0 && c->rk != 2 && c->rk != 3) { msg = "rk must be 2 or 3 (0 selects 2)"; return false; }
@@ -74,7 +74,7 @@ bool validate(const hy_config* c, std::string& msg) {
   for (int d = 0; d < 3; ++d) {
     if (c->n[d] < 1 || c->block[d] < 1) { msg = "n and block must be >= 1"; return false; }
     if (c->n[d] % c->block[d]) { msg = "block must divide n on every axis"; return false; }
-    if (c->block[d] < ng) { msg = "block must be >= the ghost depth (2 PLM, 3 PPM4/WENO-Z)"; return false; }
+    if (c->block[d] < ng) { msg = "block must be >= the ghost depth (2 PLM, 3 PPM4/PPMX/WENO-Z)"; return false; }
     if (!(c->hi[d] > c->lo[d]) || !std::isfinite(c->hi[d] - c->lo[d])) { msg = "need hi > lo"; return false; }
     for (int s = 0; s < 2; ++s)
       if (c->bc[d][s] != HY_BC_PERIODIC && c->bc[d][s] != HY_BC_OUTFLOW) { msg = "bad boundary code"; return false; }

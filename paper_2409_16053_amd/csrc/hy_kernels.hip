@@ -2,8 +2,8 @@
 //
 // One fused kernel per RK stage performs the whole reconstruct-solve-advance
 // sequence of Stone et al. 2024 (arXiv:2409.16053), Sec. 3: ghost zones,
-// cons-to-prim (Sec. 3.1, Eq. 4), PLM, PPM4 or WENO-Z reconstruction on
-// primitives, HLLC fluxes in x, y and z, the flux divergence and the
+// cons-to-prim (Sec. 3.1, Eq. 4), PLM, PPM4, PPMX or WENO-Z reconstruction
+// on primitives, HLLC fluxes in x, y and z, the flux divergence and the
 // low-storage SSP-RK stage update; the last stage also reduces the CFL time
 // step of Sec. 3, Eq. 3.
 //
@@ -191,6 +191,56 @@ __device__ __forceinline__ void weno_cell(T w0, T w1, T w2, T w3, T w4, T& left,
                    T(4) * (w3 - w2) - (w4 - w3), b.b0, b.b1, b.b2);
   left = weno_mix(w2, T(2) * (w4 - w3) - T(5) * (w3 - w2), T(2) * (w1 - w2) - (w3 - w2),
                   T(4) * (w1 - w2) - (w0 - w1), b.b2, b.b1, b.b0);
+}
+
+// PPMX (Sec. 3; the extremum-preserving limiters of Colella & Sekora 2008 as
+// used by McCorquodale & Colella). A limited second difference keeps the
+// common sign of its arguments and the smallest magnitude among the first
+// and 1.25 x the others, or is 0 when the signs differ.
+template <typename T>
+__device__ __forceinline__ T ppmx_lim3(T d, T l, T r) {
+  const bool pos = d > T(0) && l > T(0) && r > T(0);
+  const bool neg = d < T(0) && l < T(0) && r < T(0);
+  const T m = fmin(fabs(d), fmin(T(1.25) * fabs(l), T(1.25) * fabs(r)));
+  return pos ? m : (neg ? -m : T(0));
+}
+
+template <typename T>
+__device__ __forceinline__ T ppmx_lim4(T d, T c, T l, T r) {
+  const bool pos = d > T(0) && c > T(0) && l > T(0) && r > T(0);
+  const bool neg = d < T(0) && c < T(0) && l < T(0) && r < T(0);
+  const T m = fmin(fmin(fabs(d), T(1.25) * fabs(c)), fmin(T(1.25) * fabs(l), T(1.25) * fabs(r)));
+  return pos ? m : (neg ? -m : T(0));
+}
+
+// Fourth-order interface value between b and c (neighbours a, d),
+// 7/12 (b + c) - 1/12 (a + d) written in differences so that a constant state
+// is reproduced exactly; a value outside [b, c] is replaced by
+// (b + c)/2 - D/6, D the limited 3 (b - 2f + c).
+template <typename T>
+__device__ __forceinline__ T ppmx_iface(T a, T b, T c, T d) {
+  const T f = T(0.5) * (b + c) - ((a - b) + (d - c)) / T(12);
+  const T g = T(0.5) * (b + c) - ppmx_lim3(T(3) * (b - T(2) * f + c), a - T(2) * b + c, b - T(2) * c + d) / T(6);
+  return (f - b) * (c - f) < T(0) ? g : f;
+}
+
+// Edges (aL, aR) of the cell w2 of (w0..w4) from its interface values: at an
+// extremum both edge offsets are scaled by limited / unlimited curvature,
+// elsewhere an offset larger than twice the other is cut to twice it.
+template <typename T>
+__device__ __forceinline__ void ppmx_cell(T w0, T w1, T w2, T w3, T w4, T& aL, T& aR) {
+  const T dm = w2 - aL, dp = aR - w2;
+  const bool ext = dm * dp <= T(0) || (w3 - w2) * (w2 - w1) <= T(0);
+  const T d2 = T(6) * (aL + aR - T(2) * w2);
+  const T lim = ppmx_lim4(d2, w1 - T(2) * w2 + w3, w0 - T(2) * w1 + w2, w2 - T(2) * w3 + w4);
+  // a true division: d2 can be tiny (a curvature of velocity noise), where
+  // a reciprocal of a subnormal would overflow
+  const T ratio = d2 != T(0) ? lim / d2 : T(0);
+  const T eL = w2 - ratio * dm, eR = w2 + ratio * dp;
+  const T mR = fabs(dp) >= T(2) * fabs(dm) ? w2 + T(2) * dm : aR;
+  const T mL = fabs(dm) >= T(2) * fabs(dp) ? w2 - T(2) * dp : aL;
+  aL = ext ? eL : mL;
+  aR = ext ? eR : mR;
 }
 
 // --------------------------------------------------------------- HLLC
@@ -412,6 +462,14 @@ struct ZQueue<2, T> {       // WENO-Z
 };
 
 template <typename T>
+struct ZQueue<3, T> {       // PPMX
+  T wm[5], w0[5], w1[5], w2[5];  // primitives at k-1, k, k+1, k+2
+  T a1[5];                  // limited interface value at k+1/2
+  T ar0[5];                 // right edge of cell k
+  double fm[5];
+};
+
+template <typename T>
 __device__ __forceinline__ void zflux(const Gas<T>& g, const T wl[5], const T wr[5], double f[5]) {
   // z-normal: (n, t1, t2) = (vz, vx, vy)
   T h[5];
@@ -426,7 +484,7 @@ __device__ __forceinline__ void zflux(const Gas<T>& g, const T wl[5], const T wr
 // ------------------------------------------------------------ one face
 // Flux through the face between LDS cells (base - STR) and base along
 // direction DIR (0 = x, 1 = y), in conserved-variable order. PLM reads two
-// cells on each side, PPM4 and WENO-Z three.
+// cells on each side, PPM4, PPMX and WENO-Z three.
 template <int RECON, int DIR, typename T, int STR, int PLANE>
 __device__ __forceinline__ void face_flux(const Gas<T>& gas, const T* __restrict__ sW, int base,
                                           T out[5]) {
@@ -443,6 +501,16 @@ __device__ __forceinline__ void face_flux(const Gas<T>& gas, const T* __restrict
       const T c3 = s[0], c4 = s[STR], c5 = s[2 * STR];
       wl[v] = weno_right(c0, c1, c2, c3, c4);  // right face of cell c2
       wr[v] = weno_right(c5, c4, c3, c2, c1);  // left face of cell c3 (mirrored)
+    } else if constexpr (RECON == 3) {
+      const T c0 = s[-3 * STR], c1 = s[-2 * STR], c2 = s[-STR];
+      const T c3 = s[0], c4 = s[STR], c5 = s[2 * STR];
+      const T im = ppmx_iface(c0, c1, c2, c3), i0 = ppmx_iface(c1, c2, c3, c4);
+      const T ip = ppmx_iface(c2, c3, c4, c5);
+      T l2 = im, r2 = i0, l3 = i0, r3 = ip;
+      ppmx_cell(c0, c1, c2, c3, c4, l2, r2);
+      ppmx_cell(c1, c2, c3, c4, c5, l3, r3);
+      wl[v] = r2;
+      wr[v] = l3;
     } else {
       const T c0 = s[-3 * STR], c1 = s[-2 * STR], c2 = s[-STR];
       const T c3 = s[0], c4 = s[STR], c5 = s[2 * STR];
@@ -589,6 +657,33 @@ k_stage(const StageArgs a) {
           zq.s0[v] = sc;
         }
         zflux(gas, wl, wr, zq.fm);
+      } else if constexpr (RECON == 3) {
+        double u[5];
+        T c[6][5];
+#pragma unroll
+        for (int o = 0; o < 6; ++o) {
+          col_load(k0 - 3 + o, u);
+          to_prim(u, c[o], k0 - 3 + o);
+        }
+        T wl[5], wr[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const T im = ppmx_iface(c[0][v], c[1][v], c[2][v], c[3][v]);  // k0-3/2
+          const T i0 = ppmx_iface(c[1][v], c[2][v], c[3][v], c[4][v]);  // k0-1/2
+          const T ip = ppmx_iface(c[2][v], c[3][v], c[4][v], c[5][v]);  // k0+1/2
+          T l2 = im, r2 = i0, l3 = i0, r3 = ip;
+          ppmx_cell(c[0][v], c[1][v], c[2][v], c[3][v], c[4][v], l2, r2);  // cell k0-1
+          ppmx_cell(c[1][v], c[2][v], c[3][v], c[4][v], c[5][v], l3, r3);  // cell k0
+          wl[v] = r2;
+          wr[v] = l3;
+          zq.ar0[v] = r3;
+          zq.a1[v] = ip;
+          zq.wm[v] = c[2][v];
+          zq.w0[v] = c[3][v];
+          zq.w1[v] = c[4][v];
+          zq.w2[v] = c[5][v];
+        }
+        zflux(gas, wl, wr, zq.fm);
       } else if constexpr (RECON == 2) {
         double u[5];
         T c[6][5];
@@ -730,6 +825,29 @@ k_stage(const StageArgs a) {
             zq.w0[v] = zq.w1[v];
             zq.w1[v] = w2[v];
             zq.s0[v] = s1[v];
+          }
+        } else if constexpr (RECON == 3) {
+          T w3[5];
+          to_prim(un, w3, k + 3);
+          T wl[5], wr[5], r1[5], a2[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            a2[v] = ppmx_iface(zq.w0[v], zq.w1[v], zq.w2[v], w3[v]);  // k+3/2
+            T l1 = zq.a1[v];
+            r1[v] = a2[v];
+            ppmx_cell(zq.wm[v], zq.w0[v], zq.w1[v], zq.w2[v], w3[v], l1, r1[v]);  // cell k+1
+            wl[v] = zq.ar0[v];
+            wr[v] = l1;
+          }
+          zflux(gas, wl, wr, fz);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            zq.wm[v] = zq.w0[v];
+            zq.w0[v] = zq.w1[v];
+            zq.w1[v] = zq.w2[v];
+            zq.w2[v] = w3[v];
+            zq.a1[v] = a2[v];
+            zq.ar0[v] = r1[v];
           }
         } else if constexpr (RECON == 2) {
           T w3[5];
@@ -883,6 +1001,15 @@ __device__ void face_pair(const Geo& geo, const Floors& fl, const Gas<T>& gas,
     } else if constexpr (RECON == 2) {
       wl[v] = weno_right(c[0][v], c[1][v], c[2][v], c[3][v], c[4][v]);
       wr[v] = weno_right(c[5][v], c[4][v], c[3][v], c[2][v], c[1][v]);
+    } else if constexpr (RECON == 3) {
+      const T im = ppmx_iface(c[0][v], c[1][v], c[2][v], c[3][v]);
+      const T i0 = ppmx_iface(c[1][v], c[2][v], c[3][v], c[4][v]);
+      const T ip = ppmx_iface(c[2][v], c[3][v], c[4][v], c[5][v]);
+      T l2 = im, r2 = i0, l3 = i0, r3 = ip;
+      ppmx_cell(c[0][v], c[1][v], c[2][v], c[3][v], c[4][v], l2, r2);
+      ppmx_cell(c[1][v], c[2][v], c[3][v], c[4][v], c[5][v], l3, r3);
+      wl[v] = r2;
+      wr[v] = l3;
     } else {
       const T d1 = ppm_dm(c[0][v], c[1][v], c[2][v]), d2 = ppm_dm(c[1][v], c[2][v], c[3][v]);
       const T d3 = ppm_dm(c[2][v], c[3][v], c[4][v]), d4 = ppm_dm(c[3][v], c[4][v], c[5][v]);
@@ -1143,11 +1270,12 @@ __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32
    {HY_K(R, float, TX, TY, W, 1), HY_K(R, float, TX, TY, W, 2)}}
 #define HY_STAGE_SET(TX, TY, W)                                                       \
   {TX, TY, W,                                                                         \
-   {HY_RECON_SET(0, TX, TY, W), HY_RECON_SET(1, TX, TY, W), HY_RECON_SET(2, TX, TY, W)}}
+   {HY_RECON_SET(0, TX, TY, W), HY_RECON_SET(1, TX, TY, W), HY_RECON_SET(2, TX, TY, W),     \
+    HY_RECON_SET(3, TX, TY, W)}}
 
 struct StageVariant {
   int tx, ty, wpe;
-  const void* fn[3][2][2];  // [recon][precision][kind: first stage, later stage]
+  const void* fn[4][2][2];  // [recon][precision][kind: first stage, later stage]
 };
 
 static const StageVariant kStageVariants[] = {
@@ -1177,10 +1305,11 @@ hipError_t launch_stage(int v, int recon, int prec, int kind, const StageArgs& a
 }
 
 hipError_t launch_fofc(int recon, int prec, const FixArgs& a, int grid_x, hipStream_t s) {
-  static const void* fix[3][2] = {
+  static const void* fix[4][2] = {
       {(const void*)&k_fofc_fix<0, double>, (const void*)&k_fofc_fix<0, float>},
       {(const void*)&k_fofc_fix<1, double>, (const void*)&k_fofc_fix<1, float>},
-      {(const void*)&k_fofc_fix<2, double>, (const void*)&k_fofc_fix<2, float>}};
+      {(const void*)&k_fofc_fix<2, double>, (const void*)&k_fofc_fix<2, float>},
+      {(const void*)&k_fofc_fix<3, double>, (const void*)&k_fofc_fix<3, float>}};
   void* args[] = {(void*)&a};
   hipError_t e = hipLaunchKernel(fix[recon][prec], dim3(grid_x, a.nprob), dim3(256), args, 0, s);
   if (e != hipSuccess || !a.any_last) return e;

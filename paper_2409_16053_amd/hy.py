@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhy.so")
 
 HY_OK, HY_ERR_ARG, HY_ERR_NOMEM, HY_ERR_HIP, HY_ERR_STATE, HY_ERR_BUDGET = range(6)
 PERIODIC, OUTFLOW = 0, 1
-PLM, PPM4, WENOZ = 0, 1, 2
+PLM, PPM4, WENOZ, PPMX = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 HOST, DEVICE, HOST_PINNED = 0, 1, 2
 

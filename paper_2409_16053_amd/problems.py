@@ -263,12 +263,15 @@ def turbulence(N=256, seed=1, kmin=1, kmax=16, mach=0.5, rho=1.0, p=1.0,
 # --------------------------------------------------------------------------
 # Kelvin-Helmholtz shear layer
 # --------------------------------------------------------------------------
-def kelvin_helmholtz(N=512, seed=2, n=None, gamma=5.0 / 3.0, noise=1e-2, **kw):
+def kelvin_helmholtz(N=512, seed=2, n=None, gamma=5.0 / 3.0, noise=1e-2, bg_noise=0.0, **kw):
     """Sharp double shear layer on [-1/2, 1/2]^3 with seeded vy noise.
 
     |y| < 1/4: rho = 2, vx = +1/2; elsewhere rho = 1, vx = -1/2; p = 2.5.
     Where ||y| - 1/4| < 0.05, vy = noise * (2 r - 1) with r the SplitMix64
-    draw for (seed, global cell index i + nx (j + ny k)).
+    draw for (seed, global cell index i + nx (j + ny k)). ``bg_noise`` > 0
+    also multiplies rho, vx and p everywhere by independent factors
+    1 + bg_noise (2 r - 1) (counters offset by 1, 2 and 3 times the cell
+    count), so that no two cells hold exactly equal values.
     """
     if n is None:
         n = (N, N, N)
@@ -290,7 +293,14 @@ def kelvin_helmholtz(N=512, seed=2, n=None, gamma=5.0 / 3.0, noise=1e-2, **kw):
         i = np.arange(nx, dtype=np.uint64)[None, None, :]
         idx = i + np.uint64(nx) * (j + np.uint64(ny) * k)
         vy[:, rows, :] = noise * (2.0 * uniform01(seed, idx) - 1.0)
-    U = conserved(rho, vx, vy, 0.0, np.full(shape, 2.5), gamma)
+    pres = np.full(shape, 2.5)
+    if bg_noise > 0.0:
+        ncell = nx * ny * nz
+        idx = np.arange(ncell, dtype=np.uint64).reshape(shape)
+        fac = [1.0 + bg_noise * (2.0 * uniform01(seed, idx + np.uint64(m * ncell)) - 1.0)
+               for m in (1, 2, 3)]
+        rho, vx, pres = rho * fac[0], vx * fac[1], pres * fac[2]
+    U = conserved(rho, vx, vy, 0.0, pres, gamma)
     bcs = ((PERIODIC, PERIODIC),) * 3
     return Problem(n=tuple(n), lo=lo, hi=hi, bc=bcs, U=U, gamma=gamma,
                    name="kelvin_helmholtz", meta=dict(seed=seed), **kw)

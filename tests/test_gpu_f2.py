@@ -1,5 +1,5 @@
-"""GPU parity of the higher-order options: WENO-Z reconstruction and the
-three-stage SSP-RK integrator, against the CPU reference solver.
+"""GPU parity of the higher-order options: WENO-Z and PPMX reconstruction
+and the three-stage SSP-RK integrator, against the CPU reference solver.
 
 FP64 gate: rel L1 <= 1e-12 and per-variable elementwise agreement <= 1e-9 of
 the variable's largest magnitude; mixed precision: rel L1 <= 1e-5 against the
@@ -60,23 +60,38 @@ def _check(hy, pb, steps, label, **kw):
     return U, q, ref
 
 
-@pytest.mark.parametrize("recon,rk", [(P.WENOZ, 3), (P.WENOZ, 2), (P.PLM, 3), (P.PPM4, 3)])
+@pytest.mark.parametrize("recon,rk", [(P.WENOZ, 3), (P.WENOZ, 2), (P.PLM, 3), (P.PPM4, 3), (P.PPMX, 3),
+                                     (P.PPMX, 2)])
 def test_turbulence_schemes(hy, recon, rk):
     pb = P.turbulence(N=48, seed=3, kmax=8).with_(block=(16, 16, 24), recon=recon, rk=rk)
     _check(hy, pb, 8, f"turb {recon}/{rk}")
 
 
-def test_kh_wenoz_rk3_ragged_tiles(hy):
-    # 40 x 24 x 24 blocks: no tile shape divides 40, so the x tiles are ragged
-    pb = P.kelvin_helmholtz(n=(80, 48, 24), seed=5).with_(block=(40, 24, 24), recon=P.WENOZ, rk=3)
-    _check(hy, pb, 6, "kh wenoz ragged")
+@pytest.mark.parametrize("recon", [P.WENOZ, P.PPMX])
+def test_kh_rk3_ragged_tiles(hy, recon):
+    # 40 x 24 x 24 blocks: no tile shape divides 40, so the x tiles are ragged.
+    # PPMX's extremum test switches discontinuously where a cell equals its
+    # neighbour exactly (the KH layer's untouched vx = -1/2 plateaus), so a
+    # rounding difference picks a different, equally valid branch; a 1e-6
+    # perturbation of every cell removes exact ties
+    pb = P.kelvin_helmholtz(n=(80, 48, 24), seed=5, bg_noise=1e-6).with_(block=(40, 24, 24),
+                                                                          recon=recon, rk=3)
+    _check(hy, pb, 6, f"kh {recon} ragged")
 
 
+@pytest.mark.parametrize("recon", [P.WENOZ, P.PPMX])
 @pytest.mark.parametrize("axis", [0, 1, 2])
-def test_sod_wenoz_rk3_each_axis(hy, axis):
-    pb = P.sod(N=64, axis=axis, ntrans=8).with_(block=(8, 8, 8), recon=P.WENOZ, rk=3)
+def test_sod_rk3_each_axis(hy, axis, recon):
+    pb = P.sod(N=64, axis=axis, ntrans=8).with_(block=(8, 8, 8), recon=recon, rk=3)
     pb = pb.with_(block=tuple(32 if pb.n[d] == 64 else 8 for d in range(3)))
-    _check(hy, pb, 20, f"sod wenoz axis {axis}")
+    _check(hy, pb, 20, f"sod {recon} axis {axis}")
+
+
+def test_sedov_outflow_ppmx_rk3(hy):
+    # PPMX's extremum tests compare products with 0, which an exactly
+    # symmetric blast puts exactly at 0: break the symmetry as for WENO-Z
+    pb = P.sedov(N=32, seed=7, noise=1e-6).with_(block=(16, 16, 16), recon=P.PPMX, rk=3)
+    _check(hy, pb, 12, "sedov ppmx")
 
 
 def test_sedov_outflow_wenoz_rk3(hy):
@@ -88,7 +103,7 @@ def test_sedov_outflow_wenoz_rk3(hy):
     _check(hy, pb, 12, "sedov wenoz")
 
 
-@pytest.mark.parametrize("recon", [P.WENOZ, P.PPM4])
+@pytest.mark.parametrize("recon", [P.WENOZ, P.PPM4, P.PPMX])
 def test_fofc_hypersonic_rk3(hy, recon):
     pb = P.turbulence(N=32, seed=5, kmax=8, mach=20).with_(block=(16, 16, 16), recon=recon, rk=3,
                                                            fofc=1)
@@ -96,13 +111,15 @@ def test_fofc_hypersonic_rk3(hy, recon):
     assert ref["fofc_cells"] > 0
 
 
-def test_entropy_wave_fifth_order_on_gpu(hy):
+@pytest.mark.parametrize("recon,order", [(P.WENOZ, 4.5), (P.PPMX, 3.8)])
+def test_entropy_wave_high_order_on_gpu(hy, recon, order):
     # entropy waves are exact at any amplitude: the GPU path on its own
-    # reproduces the fifth order of WENO-Z (y-axis wave, several blocks)
+    # reproduces the fifth order of WENO-Z and the fourth of PPMX (y-axis
+    # wave, several blocks)
     errs = []
     for N in (16, 32, 64):
         pb = P.entropy_wave(N=N, amp=0.2, axis=1, ntrans=8).with_(block=(8, N // 2, 8),
-                                                                   recon=P.WENOZ, rk=3, cfl=0.05)
+                                                                   recon=recon, rk=3, cfl=0.05)
         g = hy.Problem(pb).set_state()
         while True:
             q = g.query()
@@ -114,23 +131,25 @@ def test_entropy_wave_fifth_order_on_gpu(hy):
         ex = P.entropy_wave(N=N, amp=0.2, axis=1, ntrans=8, t=q["t"]).U
         errs.append(float(np.abs(U[0] - ex[0]).mean() / 0.2))
     r = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
-    print(f"[entropy wave gpu] errs {errs} rates {r}", flush=True)
-    assert np.all(r >= 4.5)
+    print(f"[entropy wave gpu {recon}] errs {errs} rates {r}", flush=True)
+    assert np.all(r >= order)
 
 
-@pytest.mark.parametrize("case", ["turb_wenoz", "kh_wenoz", "sedov_wenoz"])
-def test_mixed_wenoz_rk3_vs_fp64_reference(hy, case):
-    if case == "turb_wenoz":
+@pytest.mark.parametrize("case", ["turb_wenoz", "kh_wenoz", "sedov_wenoz", "turb_ppmx", "sedov_ppmx"])
+def test_mixed_rk3_vs_fp64_reference(hy, case):
+    recon = P.PPMX if case.endswith("ppmx") else P.WENOZ
+    if case.startswith("turb"):
         pb, steps = P.turbulence(N=48, seed=1).with_(block=(24, 24, 24)), 10
-    elif case == "kh_wenoz":
+    elif case.startswith("kh"):
         pb, steps = P.kelvin_helmholtz(N=48, seed=2).with_(block=(24, 24, 24)), 10
     else:
         # FP32 cannot resolve a 1e-6 break of the blast's mirror symmetry well
         # enough for WENO-Z's weights (tau5 ~ 0 on near-symmetric stencils):
         # there mixed precision departs from FP64 at the 1e-4 level; a 1e-3
         # break keeps it at 1e-7
-        pb, steps = P.sedov(N=32, seed=3, noise=1e-3).with_(block=(16, 16, 16)), 20
-    pb = pb.with_(recon=P.WENOZ, rk=3)
+        noise = 1e-3 if recon == P.WENOZ else 1e-6
+        pb, steps = P.sedov(N=32, seed=3, noise=noise).with_(block=(16, 16, 16)), 20
+    pb = pb.with_(recon=recon, rk=3)
     ref = oracle.advance(pb, steps)
     U, _ = _run(hy, pb.with_(precision=P.MIXED), steps)
     r = _rel(U, ref["U"])
@@ -138,15 +157,16 @@ def test_mixed_wenoz_rk3_vs_fp64_reference(hy, case):
     assert r <= 1e-5
 
 
-def test_wenoz_rk3_every_tile_shape_bitwise(hy):
-    pb = P.turbulence(N=32, seed=9, kmax=8).with_(block=(32, 32, 32), recon=P.WENOZ, rk=3)
+@pytest.mark.parametrize("recon", [P.WENOZ, P.PPMX])
+def test_rk3_every_tile_shape_bitwise(hy, recon):
+    pb = P.turbulence(N=32, seed=9, kmax=8).with_(block=(32, 32, 32), recon=recon, rk=3)
     outs = [_run(hy, pb, 5, variant=v, kc=kc)[0]
             for v in range(len(hy.variants())) for kc in (32, 7, 1)]
     for U in outs[1:]:
         assert np.array_equal(U, outs[0])
 
 
-@pytest.mark.parametrize("recon", [P.PLM, P.PPM4, P.WENOZ])
+@pytest.mark.parametrize("recon", [P.PLM, P.PPM4, P.WENOZ, P.PPMX])
 @pytest.mark.parametrize("prec", [P.FP64, P.MIXED])
 def test_uniform_state_rk3(hy, recon, prec):
     pb = P.uniform(n=(32, 24, 16), rho=1.3, v=(0.3, -0.2, 0.4), p=0.8, bc=P.PERIODIC)

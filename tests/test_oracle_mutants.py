@@ -46,8 +46,8 @@ MUTANTS = [
     ("wenoz_indicator_index", "0.25 * (w[1] - w[3]) * (w[1] - w[3])", "0.25 * (w[1] - w[2]) * (w[1] - w[2])"),
     ("wenoz_left_not_mirrored", "const double m[5] = {w[4], w[3], w[2], w[1], w[0]};",
      "const double m[5] = {w[0], w[1], w[2], w[3], w[4]};"),
-    ("ppmx_second_order_interface", "7.0 / 12.0 * (b + c) - 1.0 / 12.0 * (a + d)",
-     "0.5 * (b + c) + 0.0 * (a + d)"),
+    ("ppmx_second_order_interface", "0.5 * (b + c) - ((a - b) + (d - c)) / 12.0",
+     "0.5 * (b + c) - 0.0 * ((a - b) + (d - c)) / 12.0"),
     ("ppmx_ratio_sign", "aL = a - ratio * dm;", "aL = a + ratio * dm;"),
     ("ppmx_overshoot_factor", "aR = a + 2.0 * dm;", "aR = a + 3.0 * dm;"),
     ("ppmx_limiter_constant", "#define OR_PPMX_C 1.25", "#define OR_PPMX_C 0.75"),
