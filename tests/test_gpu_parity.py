@@ -74,7 +74,34 @@ def check_fp64(hy, pb, steps, label, **kw):
 # ------------------------------------------------------------ the workloads
 def test_eigenmode_32_fp64(hy):
     pb, steps = P.workload_eigenmode_32()
-    check_fp64(hy, pb, steps, "eigenmode32")
+    U, q, _ = check_fp64(hy, pb, steps, "eigenmode32")
+    # and against the closed form at the reached time (amplitude-relative L1)
+    ex = P.sound_wave(N=32, amp=1e-6, t=q["t"]).U
+    err = float(np.abs(U[0] - ex[0]).mean() / 1e-6)
+    print(f"[eigenmode32] L1(rho) vs closed form / amplitude = {err:.3e} at t = {q['t']:.6f}", flush=True)
+    assert err < 0.05
+
+
+def test_eigenmode_second_order_on_gpu(hy):
+    # the GPU path on its own, against the closed-form eigenmode after one
+    # period (the paper's linear-wave test, Sec. 3.1): second order for PLM
+    errs = []
+    for N in (32, 64, 128):
+        pb = P.sound_wave(N=N, amp=1e-6).with_(block=(N // 2,) * 3)
+        T = pb.meta["period"]
+        g = hy.Problem(pb).set_state()
+        while True:
+            q = g.query()
+            if q["t"] + q["dt"] > T:
+                break
+            g.advance(1)
+        U = g.get_state()
+        g.close()
+        ex = P.sound_wave(N=N, amp=1e-6, t=q["t"]).U
+        errs.append(float(np.abs(U[0] - ex[0]).mean()))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    print(f"[eigenmode gpu] L1 {errs} rates {rates}", flush=True)
+    assert np.all(rates >= 1.8)
 
 
 def test_turbulence_64_every_tile_shape(hy):
