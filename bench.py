@@ -211,6 +211,17 @@ def main():
                       f"{t1 - t0:.1f} s wall",
         }
         assert r["status"] == 0
+        # one host thread, on a 128^3 cut of the same workload (one step)
+        threads = oracle.get_threads()
+        small, _ = P.workload_turbulence_256(N=128, block=64)
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.advance(small, 1)
+        t1 = time.perf_counter()
+        oracle.set_threads(threads)
+        out["cpu_baseline"]["single_thread"] = {
+            "value": small.cells / (t1 - t0), "unit": "cell-updates/s", "cores": 1,
+            "sample": f"1 RK2 step of 128^3 turbulence (same recipe), {t1 - t0:.1f} s wall"}
 
     valu = valu_summary(cells, a1 if dom == 1 else a2, dom)
     if valu is not None:
@@ -244,9 +255,10 @@ def valu_summary(cells, avg_s, stage):
     if n is None:
         return None
     ops = 64.0 * n / avg_s
+    # wave-level instruction counts x 64 lanes = per-cell lane instructions
     return {"fp64_lane_ops_per_s": ops, "peak": FP64_LANE_OPS_PEAK, "frac": ops / FP64_LANE_OPS_PEAK,
-            "fp64_valu_insts_per_cell": n / cells,
-            "valu_insts_per_cell": c.get(f"stage{stage}_valu_insts_per_launch", 0) / cells}
+            "fp64_lane_insts_per_cell": 64.0 * n / cells,
+            "valu_lane_insts_per_cell": 64.0 * c.get(f"stage{stage}_valu_insts_per_launch", 0) / cells}
 
 
 def run_schemes(run, pb, P, steps):
@@ -339,12 +351,29 @@ def run_batch_workload(hy, P, torch, count=48, seed=3):
         else:
             g.set_launch(*tuned[key][:2])
     torch.cuda.synchronize()
-    # one at a time
+    # one at a time, each in its own tuned shape
     t0 = time.perf_counter()
     for g in gs:
         g.advance(steps)
         torch.cuda.synchronize()
     t_one = time.perf_counter() - t0
+    # the batch shares one tile shape per launch: tune it for the batch as a
+    # whole (each problem keeps its own z-chunk), timing two batched steps
+    own = [g.get_launch() for g in gs]
+    best = None
+    for v in range(len(hy.variants())):
+        for g, (_, kc) in zip(gs, own):
+            g.set_launch(v, kc)
+        hy.batch_advance(gs, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hy.batch_advance(gs, 2)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        if best is None or t < best[0]:
+            best = (t, v)
+    for g, (_, kc) in zip(gs, own):
+        g.set_launch(best[1], kc)
     for g in gs:
         g.set_state()
     torch.cuda.synchronize()
@@ -382,6 +411,7 @@ def run_batch_workload(hy, P, torch, count=48, seed=3):
         "steps": steps,
         "dtype": "mixed",
         "size_classes": {f"{k[0]}^3": list(v[:2]) for k, v in tuned.items()},
+        "batch_tile_variant": list(hy.variants()[best[1]]),
         "floor_hits": floors,
     }
 
