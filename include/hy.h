@@ -98,16 +98,20 @@ typedef struct {
   double rho_floor, p_floor;
 } hy_config;
 
-/* Device bytes one problem needs: two FP64 state registers of 5 x cells
- * doubles each (the step-start state and the RK stage state; three with
- * rk = 3), a 512-byte header, and with fofc one byte of flag per cell. Returns 0 for an invalid
- * configuration. */
+/* Device bytes one problem needs (the MeshBlockPack of Sec. 2, "Data
+ * locality", with no stored ghost cells): two FP64 state registers of
+ * 5 x cells doubles each (the step-start state and the RK stage state; three
+ * with rk = 3), a 512-byte header, and with fofc one byte of flag per cell.
+ * Returns 0 for an invalid configuration (message in hy_last_error). */
 size_t hy_workspace_bytes(const hy_config* cfg);
 
-/* Create a problem in the caller's device workspace `dev_ws` (256-byte
- * aligned, at least hy_workspace_bytes(cfg) bytes, on the current device).
- * Writes the header synchronously. *out receives the handle. The state is
- * undefined until hy_set_state. */
+/* Create a problem (a mesh of equal MeshBlocks, Sec. 2) in the caller's
+ * device workspace `dev_ws` (256-byte aligned, at least hy_workspace_bytes(cfg)
+ * bytes, on the current device; the caller keeps ownership and must keep it
+ * alive until hy_destroy). Writes the header synchronously. *out receives the
+ * handle. The state is undefined until hy_set_state. Errors: HY_ERR_ARG for an
+ * invalid configuration or workspace pointer, HY_ERR_NOMEM for a workspace
+ * smaller than hy_workspace_bytes, HY_ERR_HIP if the header upload fails. */
 hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_problem** out);
 
 /* Where a state buffer lives (the `where` argument of hy_set_state and
@@ -134,14 +138,21 @@ hy_status hy_set_state(hy_problem* p, const double* U, int where, void* hip_stre
  * copy (check the flag later with hy_query). */
 hy_status hy_get_state(hy_problem* p, double* U, int where, void* hip_stream);
 
-/* Advance nsteps >= 0 full RK2 steps (async). Each step uses the time step
- * computed on the device at the end of the previous one; the host never reads
- * it back. */
+/* Advance nsteps >= 0 full time steps (async): the reconstruct-solve-advance
+ * update of Sec. 3 in each stage of the configured SSP-RK integrator (method
+ * of lines), FOFC after each stage when enabled, and the CFL time step of
+ * Eq. 3 for the next step. Each step uses the time step computed on the
+ * device at the end of the previous one; the host never reads it back.
+ * Errors on the device (non-finite state, rho <= 0) surface at the next
+ * hy_query or hy_get_state. */
 hy_status hy_advance(hy_problem* p, int32_t nsteps, void* hip_stream);
 
-/* Advance n problems together (async): problem q runs nsteps[q] steps. For
- * every step index, one launch per RK stage covers the tiles of all problems
- * still running that share a (reconstruction, precision) pair. Per-cell
+/* Advance n problems together (async): problem q runs nsteps[q] steps (the
+ * MeshBlockPack of Sec. 2 extended to the blocks of many meshes). For every
+ * step index, one launch per RK stage covers the tiles of all problems still
+ * running that share a (reconstruction, precision) pair; problems of
+ * different integrators share the stages they have in common. No problem
+ * may appear twice; all must live on the current device. Per-cell
  * arithmetic is identical to hy_advance, so results are bitwise equal to
  * running each problem alone. */
 hy_status hy_batch_advance(hy_problem* const* ps, const int32_t* nsteps, int32_t n,
@@ -161,8 +172,8 @@ hy_status hy_batch_advance_graph(hy_problem* const* ps, const int32_t* nsteps, i
                                  void* hip_stream);
 
 /* Wait for the problem's last stream, then read its time, the time step the
- * next step will take, the steps taken, the floor hits and the cells corrected
- * by FOFC (summed over stages; any pointer may be NULL). Returns HY_ERR_STATE
+ * next step will take (Eq. 3), the steps taken, the floor hits and the cells
+ * corrected by FOFC (Sec. 3; summed over stages; any pointer may be NULL). Returns HY_ERR_STATE
  * if the device flagged a bad state. */
 hy_status hy_query(hy_problem* p, double* t, double* dt_next, int64_t* steps,
                    int64_t* floor_hits, int64_t* fofc_cells);

@@ -15,6 +15,7 @@
  *   -> HLLC Riemann fluxes in x, y and z (Sec. 3; Toro's textbook, Ch. 10)
  *   -> flux divergence and a low-storage SSP-RK stage (Sec. 3, method of lines;
  *      one, two or three stages)
+ *   -> optionally, first-order flux correction with LLF fluxes (Sec. 3, FOFC)
  *   -> CFL time step, Eq. 3: CFL times the minimum over all cells and all
  *      dimensions of dx_d / lambda_max,d.
  * It works on the whole mesh with no MeshBlock decomposition: splitting the
@@ -24,7 +25,9 @@
  * design notes): PLM uses the van Leer harmonic-mean limiter; PPM4 is
  * Colella & Woodward (1984) Eqs. 1.6-1.10 without steepening or flattening;
  * WENO-Z uses the Jiang-Shu smoothness indicators with the squared WENO-Z
- * weights of Borges et al. (2008);
+ * weights of Borges et al. (2008); PPMX uses the extremum-preserving limiters
+ * of Colella & Sekora (2008); LLF is Rusanov's flux; FOFC replaces the fluxes
+ * on all faces of a cell whose stage result has rho or p <= 0;
  * the reconstructed energy variable is u_g; HLLC is Toro-Spruce-Speares with
  * PVRS pressure-based wave speeds; RK2 is SSPRK(2,2) and RK3 SSPRK(3,3) of
  * Shu & Osher, both in two-register low-storage form;
