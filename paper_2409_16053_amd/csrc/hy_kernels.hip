@@ -1146,7 +1146,7 @@ __global__ void __launch_bounds__(256) k_fofc_fix(const FixArgs a) {
   }
 }
 
-// After a corrected stage 2: the time step from the corrected state.
+// After a corrected last stage: the time step from the corrected state.
 __global__ void __launch_bounds__(256) k_fofc_dt(const FixArgs a) {
   const FixEntry E = a.e[blockIdx.y];
   const DevProblem& P = *E.p;

@@ -263,14 +263,14 @@ class Problem:
 
     def autotune(self, full_steps=0, stream=None):
         """Pick the fastest compiled variant and z-chunk (see hy_autotune).
-        full_steps > 0 times whole RK2 steps and advances the state."""
+        full_steps > 0 times whole RK steps and advances the state."""
         v, k, us = _c.c_int32(), _c.c_int32(), _c.c_double()
         _check(lib().hy_autotune(self.h, _stream(stream), int(full_steps), _c.byref(v), _c.byref(k),
                                  _c.byref(us)))
         return v.value, k.value, us.value
 
     def autotune_steps(self, full_steps=2):
-        """Tune on whole RK2 steps using a scratch copy of this problem, then
+        """Tune on whole RK steps using a scratch copy of this problem, then
         apply the choice here (this problem's state is left unchanged)."""
         scratch = Problem(self.pb, device=self.device)
         scratch.set_state(self.get_state(device=True))
