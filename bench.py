@@ -48,10 +48,17 @@ FP64_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with comments and blank lines removed (a
+    comment edit does not change the kernels the counters were taken on)."""
+    import re
     h = hashlib.sha256()
     for f in ("hy_kernels.hip", "hy_internal.h"):
-        with open(os.path.join(ROOT, "paper_2409_16053_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2409_16053_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        src = "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+        h.update(src.encode())
     return h.hexdigest()[:16]
 
 
