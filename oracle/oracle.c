@@ -639,7 +639,8 @@ typedef struct {
  * (Sec. 3 cites Ketcheson 2010 for the family):
  *   RK1 forward Euler:            (0, 1, 1)
  *   RK2 SSPRK(2,2):               (0, 1, 1), (1/2, 1/2, 1/2)
- *   RK3 SSPRK(3,3) (Shu & Osher): (0, 1, 1), (3/4, 1/4, 1/4), (1/3, 2/3, 2/3) */
+ *   RK3 SSPRK(3,3) (Shu & Osher): (0, 1, 1), (3/4, 1/4, 1/4), (1/3, 2/3, 2/3)
+ * (RK4 is SSPRK(10,4), in or_advance.) */
 static rk_coef rk_stage(int rk, int stage) {
   rk_coef k = {0.0, 1.0, 1.0};
   if (stage == 1) return k;
@@ -656,9 +657,9 @@ static rk_coef rk_stage(int rk, int stage) {
 static void stage_formula(const or_params* p, const work* w, rk_coef k, const double* U0,
                           const double* Ust, double h, double* Uout) {
   const size_t nt = 5 * ncell(p);
-  if (k.a == 0.0) {  /* first stage: Ust + h L */
+  if (k.a == 0.0) {  /* Ust + c h L */
 #pragma omp parallel for schedule(static)
-    for (size_t c = 0; c < nt; ++c) Uout[c] = Ust[c] + h * w->L[c];
+    for (size_t c = 0; c < nt; ++c) Uout[c] = Ust[c] + k.c * h * w->L[c];
   } else {
 #pragma omp parallel for schedule(static)
     for (size_t c = 0; c < nt; ++c) Uout[c] = k.a * U0[c] + k.b * Ust[c] + k.c * h * w->L[c];
@@ -720,10 +721,11 @@ static long long stage_apply(const or_params* p, work* w, rk_coef k, const doubl
  * low-storage SSP-RK of the Ketcheson 2010 family; p->rk stages). With RK2:
  *   U1      = Un + dt L(Un)
  *   U(n+1)  = Un/2 + U1/2 + dt L(U1)/2
- * and with RK3:
+ * with RK3:
  *   U1      = Un + dt L(Un)
  *   U2      = 3/4 Un + 1/4 U1 + 1/4 dt L(U1)
  *   U(n+1)  = 1/3 Un + 2/3 U2 + 2/3 dt L(U2)
+ * and with RK4 the ten-stage SSPRK(10,4) spelled out below.
  * (each stage followed by FOFC when enabled), then dt for the next step from
  * U(n+1). *dt carries the step size in and the next one out; *t,
  * *floor_hits and *fofc_cells accumulate (either counter may be NULL).
@@ -737,25 +739,53 @@ int or_advance(const or_params* p, double* U, int nsteps, double* t, double* dt,
     if (p->n[d] < 1) return OR_ERR_ARG;
     if ((p->bc[d][0] == OR_PERIODIC) != (p->bc[d][1] == OR_PERIODIC)) return OR_ERR_ARG;
   }
-  if (p->rk < 1 || p->rk > 3 || p->recon < OR_PLM || p->recon > OR_PPMX) return OR_ERR_ARG;
+  if (p->rk < 1 || p->rk > 4 || p->recon < OR_PLM || p->recon > OR_PPMX) return OR_ERR_ARG;
   work w;
   if (work_alloc(&w, p) != OR_OK) { work_free(&w); return OR_ERR_NOMEM; }
   const size_t nt = 5 * ncell(p);
   double* U1 = malloc(nt * sizeof(double));
   double* U2 = malloc(nt * sizeof(double));
-  if (!U1 || !U2) { free(U1); free(U2); work_free(&w); return OR_ERR_NOMEM; }
+  double* Q2 = p->rk == 4 ? malloc(nt * sizeof(double)) : NULL;
+  if (!U1 || !U2 || (p->rk == 4 && !Q2)) {
+    free(U1); free(U2); free(Q2); work_free(&w);
+    return OR_ERR_NOMEM;
+  }
   int status = OR_OK;
   long long hits = 0, fofc = 0;
   for (int s = 0; s < nsteps; ++s) {
     const double h = *dt;
     const double* st = U;  /* state the stage differentiates */
-    for (int stage = 1; stage <= p->rk; ++stage) {
-      int bad = 0;
-      hits += divergence(p, &w, st, &bad);
-      if (bad) status = OR_ERR_STATE;
-      double* out = (stage & 1) ? U1 : U2;  /* never the stage's own input */
-      fofc += stage_apply(p, &w, rk_stage(p->rk, stage), U, st, h, out);
-      st = out;
+    if (p->rk == 4) {
+      /* SSPRK(10,4) of Ketcheson (2008) in its low-storage form: nine stages
+       * q1 <- q1 + h/6 L(q1) with, after the fifth, q2 <- q2/25 + 9 q1/25 and
+       * q1 <- 15 q2 - 5 q1; then u <- q2 + 3/5 q1 + h/10 L(q1). q1 alternates
+       * between U1 and U2 so that no stage overwrites its own input. */
+      memcpy(Q2, U, nt * sizeof(double));
+      const rk_coef k16 = {0.0, 1.0, 1.0 / 6.0}, kend = {1.0, 3.0 / 5.0, 1.0 / 10.0};
+      for (int stage = 1; stage <= 10; ++stage) {
+        int bad = 0;
+        hits += divergence(p, &w, st, &bad);
+        if (bad) status = OR_ERR_STATE;
+        double* out = (stage & 1) ? U1 : U2;
+        fofc += stage_apply(p, &w, stage < 10 ? k16 : kend, Q2, st, h, out);
+        st = out;
+        if (stage == 5) {
+          double* q1 = out;
+          for (size_t c = 0; c < nt; ++c) {
+            Q2[c] = Q2[c] / 25.0 + 9.0 / 25.0 * q1[c];
+            q1[c] = 15.0 * Q2[c] - 5.0 * q1[c];
+          }
+        }
+      }
+    } else {
+      for (int stage = 1; stage <= p->rk; ++stage) {
+        int bad = 0;
+        hits += divergence(p, &w, st, &bad);
+        if (bad) status = OR_ERR_STATE;
+        double* out = (stage & 1) ? U1 : U2;  /* never the stage's own input */
+        fofc += stage_apply(p, &w, rk_stage(p->rk, stage), U, st, h, out);
+        st = out;
+      }
     }
     memcpy(U, st, nt * sizeof(double));
     *t += h;
@@ -765,6 +795,7 @@ int or_advance(const or_params* p, double* U, int nsteps, double* t, double* dt,
   if (fofc_cells) *fofc_cells += fofc;
   free(U1);
   free(U2);
+  free(Q2);
   work_free(&w);
   return status;
 }

@@ -1,5 +1,6 @@
 """Pins of the higher-order options of the CPU reference solver: WENO-Z and
-PPMX reconstruction and the one- and three-stage SSP-RK integrators (Sec. 3).
+PPMX reconstruction and the one-, three- and ten-stage (fourth-order) SSP-RK
+integrators (Sec. 3).
 
 * WENO-Z face values are exact for cell averages of quadratics (each
   third-order candidate is), converge at fifth order on smooth data, and take
@@ -237,8 +238,43 @@ def test_time_order_of_the_integrators(oracle_lib, recon, rk, N, cfls, lo_, hi_)
     assert lo_ <= r <= hi_, (errs, r)
 
 
+def _march_entropy(oracle_lib, N, rk, cfl):
+    pb = P.entropy_wave(N=N, amp=0.2).with_(recon=P.WENOZ, rk=rk, cfl=cfl)
+    return _run_to(oracle_lib, pb, 1.0)[0]
+
+
+@pytest.mark.parametrize("rk,order", [(4, 4.0), (3, 3.0), (2, 2.0)])
+def test_time_order_by_richardson(oracle_lib, rk, order):
+    # at fixed resolution the differences between runs at CFL c, c/2, c/4
+    # hold the time error only (the spatial error cancels), so their ratio
+    # gives the integrator's order: 4 for SSPRK(10,4), 3 and 2 for the others
+    c0 = 1.6 if rk == 4 else 0.8
+    rho = [_march_entropy(oracle_lib, 32, rk, c) for c in (c0, c0 / 2, c0 / 4)]
+    d = [np.abs(rho[0] - rho[1]).mean(), np.abs(rho[1] - rho[2]).mean()]
+    r = float(np.log2(d[0] / d[1]))
+    assert order - 0.2 <= r <= order + 0.25, (d, r)
+
+
+def test_rk4_takes_steps_beyond_rk3_stability(oracle_lib):
+    # SSPRK(10,4) has SSP coefficient 6: at CFL 3.2 it is still accurate on
+    # the entropy wave, where SSPRK(3,3) (coefficient 1) blows up
+    ex = P.entropy_wave(N=32, amp=0.2, t=1.0).U[0]
+    rho4 = _march_entropy(oracle_lib, 32, 4, 3.2)
+    assert np.abs(rho4 - ex).mean() / 0.2 < 1e-4
+    pb = P.entropy_wave(N=32, amp=0.2).with_(recon=P.WENOZ, rk=3, cfl=3.2)
+    U, t, dt = pb.U, 0.0, oracle_lib.new_dt(pb, pb.U)
+    blew = False
+    for _ in range(200):
+        r = oracle_lib.advance(pb, 1, U=U, t=t, dt=dt)
+        U, t, dt = r["U"], r["t"], r["dt"]
+        if not np.isfinite(U).all() or not (np.isfinite(dt) and dt > 0) or np.abs(U[0] - 1).max() > 1:
+            blew = True
+            break
+    assert blew
+
+
 @pytest.mark.parametrize("recon", [P.PLM, P.PPM4, P.WENOZ, P.PPMX])
-@pytest.mark.parametrize("rk", [1, 2, 3])
+@pytest.mark.parametrize("rk", [1, 2, 3, 4])
 def test_uniform_state_preserved(oracle_lib, recon, rk):
     # Every face sees the same two states, so L(U) = 0 exactly. RK1 and RK2
     # then return U bitwise; RK3's stage weights 3/4 + 1/4 and 1/3 + 2/3 are
@@ -252,17 +288,19 @@ def test_uniform_state_preserved(oracle_lib, recon, rk):
             assert np.array_equal(r["U"], pb.U)
         else:
             ulp = np.spacing(np.abs(pb.U))
-            assert np.all(np.abs(r["U"] - pb.U) <= 2 * rk * steps * ulp)
+            nst = {3: 3, 4: 10}[rk]
+            assert np.all(np.abs(r["U"] - pb.U) <= 4 * nst * steps * ulp)
 
 
-@pytest.mark.parametrize("recon,rk", [(P.WENOZ, 3), (P.WENOZ, 2), (P.PPM4, 3), (P.PLM, 1), (P.PPMX, 3)])
+@pytest.mark.parametrize("recon,rk", [(P.WENOZ, 3), (P.WENOZ, 2), (P.PPM4, 3), (P.PLM, 1), (P.PPMX, 3),
+                                     (P.WENOZ, 4)])
 def test_periodic_conservation_all_schemes(oracle_lib, recon, rk):
     pb = P.turbulence(N=16, seed=31, kmax=5).with_(recon=recon, rk=rk)
     steps = 4
     r = oracle_lib.advance(pb, steps)
     assert r["status"] == 0
     eps = np.finfo(np.float64).eps
-    bound = 4 * eps * np.sqrt(pb.cells * rk * steps)
+    bound = 4 * eps * np.sqrt(pb.cells * {1: 1, 2: 2, 3: 3, 4: 10}[rk] * steps)
     for v in range(5):
         scale = np.abs(pb.U[v]).sum() + np.abs(r["U"][v]).sum()
         assert abs(r["U"][v].sum() - pb.U[v].sum()) <= bound * scale, v

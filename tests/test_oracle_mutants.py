@@ -51,6 +51,8 @@ MUTANTS = [
     ("ppmx_ratio_sign", "aL = a - ratio * dm;", "aL = a + ratio * dm;"),
     ("ppmx_overshoot_factor", "aR = a + 2.0 * dm;", "aR = a + 3.0 * dm;"),
     ("ppmx_limiter_constant", "#define OR_PPMX_C 1.25", "#define OR_PPMX_C 0.75"),
+    ("rk4_combine_weight", "Q2[c] = Q2[c] / 25.0 + 9.0 / 25.0 * q1[c];", "Q2[c] = Q2[c] / 25.0 + 9.0 / 24.0 * q1[c];"),
+    ("rk4_last_step", "kend = {1.0, 3.0 / 5.0, 1.0 / 10.0}", "kend = {1.0, 3.0 / 5.0, 1.0 / 6.0}"),
     ("ghost_periodic_offset", "return bchi == OR_PERIODIC ? c % n : n - 1;",
      "return bchi == OR_PERIODIC ? (c + 1) % n : n - 1;"),
     ("ghost_outflow_index", "return bclo == OR_PERIODIC ? ((c % n) + n) % n : 0;",
@@ -107,6 +109,7 @@ def _fast_pins(O):
     yield lambda: f2.test_ppmx_no_new_extremum_at_a_jump(O)
     yield lambda: f2.test_ppmx_parabola_monotone_on_monotone_data(O)
     yield lambda: f2.test_time_order_of_the_integrators(O, P.WENOZ, 3, 256, (0.8, 0.4), 2.75, 3.3)
+    yield lambda: f2.test_time_order_by_richardson(O, 4, 4.0)
 
 
 def test_unplanted_build_passes_fast_pins(tmp_path):
