@@ -10,10 +10,10 @@
  * (Sec. 2, "MeshBlockPacks"; "Data locality"). Each step runs the paper's
  * reconstruct-solve-advance sequence (Sec. 3): ghost zones (Sec. 2,
  * "Boundary conditions"), cons-to-prim, PLM, PPM4, PPMX or WENO-Z
- * reconstruction on primitives, HLLC fluxes in x, y and z, flux divergence and a two- or
- * three-stage low-storage SSP Runge-Kutta update (method of lines), then the
- * CFL time step of Sec. 3, Eq. 3 taken as a minimum over all cells and
- * dimensions.
+ * reconstruction on primitives, HLLC fluxes in x, y and z, flux divergence
+ * and a one- to ten-stage low-storage SSP Runge-Kutta update (method of
+ * lines), optionally first-order flux correction, then the CFL time step of
+ * Sec. 3, Eq. 3 taken as a minimum over all cells and dimensions.
  *
  * Conventions for every call:
  *  - Status codes are returned; nothing throws or aborts across the ABI.
@@ -79,9 +79,10 @@ enum { HY_FP64 = 0, HY_MIXED = 1 };
  *              the fluxes on all its faces replaced by LLF fluxes of the
  *              first-order states and its stage update recomputed; 0: off.
  *              Adds 1 byte per cell to the workspace.
- *  rk          stages of the low-storage SSP Runge-Kutta integrator (Sec. 3):
- *              2 (SSPRK(2,2)) or 3 (SSPRK(3,3)); 0 selects 2. RK3 adds a
- *              third state register to the workspace.
+ *  rk          order of the low-storage SSP Runge-Kutta integrator (Sec. 3):
+ *              1 (forward Euler), 2 (SSPRK(2,2)), 3 (SSPRK(3,3)) or 4
+ *              (the ten-stage SSPRK(10,4) of Ketcheson); 0 selects 2. RK3
+ *              and RK4 add a third state register to the workspace.
  *  rho_floor, p_floor  floors applied to the primitive state only (U is
  *              never modified by a floor); each firing is counted.          */
 typedef struct {
@@ -101,7 +102,8 @@ typedef struct {
 /* Device bytes one problem needs (the MeshBlockPack of Sec. 2, "Data
  * locality", with no stored ghost cells): two FP64 state registers of
  * 5 x cells doubles each (the step-start state and the RK stage state; three
- * with rk = 3), a 512-byte header, and with fofc one byte of flag per cell.
+ * with rk = 3 or 4), a 512-byte header, and with fofc one byte of flag per
+ * cell.
  * Returns 0 for an invalid configuration (message in hy_last_error). */
 size_t hy_workspace_bytes(const hy_config* cfg);
 

@@ -2,7 +2,7 @@
 
 The hot path (ghost-zone fill, cons-to-prim, PLM/PPM4 reconstruction -- and
 PPMX or WENO-Z --, HLLC fluxes in x/y/z, flux divergence with a low-storage
-SSP-RK stage update (two or three stages), optional first-order flux
+SSP-RK stage update (RK1 to the ten-stage RK4), optional first-order flux
 correction, CFL time-step reduction) runs in hand-written HIP kernels for
 gfx950 inside ``libhy.so``, reached through the C ABI declared in
 ``include/hy.h``. ``hy`` is the thin ctypes binding; ``problems`` builds

@@ -59,7 +59,11 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int ghost_depth(int recon) { return recon == HY_PLM ? 2 : 3; }
 
-int stages_of(const hy_config* c) { return c->rk == 3 ? 3 : 2; }
+// RK stages per step and state registers per problem for each integrator.
+int stages_of(const hy_config* c) {
+  return c->rk == 1 ? 1 : (c->rk == 3 ? 3 : (c->rk == 4 ? 10 : 2));
+}
+int registers_of(const hy_config* c) { return c->rk >= 3 ? 3 : 2; }
 
 bool validate(const hy_config* c, std::string& msg) {
   if (!c) { msg = "config is NULL"; return false; }
@@ -67,7 +71,7 @@ bool validate(const hy_config* c, std::string& msg) {
     msg = "recon must be HY_PLM, HY_PPM4, HY_WENOZ or HY_PPMX";
     return false;
   }
-  if (c->rk != 0 && c->rk != 2 && c->rk != 3) { msg = "rk must be 2 or 3 (0 selects 2)"; return false; }
+  if (c->rk < 0 || c->rk > 4) { msg = "rk must be 1, 2, 3 or 4 (0 selects 2)"; return false; }
   if (c->precision != HY_FP64 && c->precision != HY_MIXED) { msg = "precision must be HY_FP64 or HY_MIXED"; return false; }
   if (c->fofc != 0 && c->fofc != 1) { msg = "fofc must be 0 or 1"; return false; }
   const int ng = ghost_depth(c->recon);
@@ -91,7 +95,7 @@ bool validate(const hy_config* c, std::string& msg) {
     return false;
   }
   const double cells = (double)c->n[0] * c->n[1] * c->n[2];
-  if (cells * 5.0 * 8.0 * stages_of(c) > 4.0e12) { msg = "mesh too large"; return false; }
+  if (cells * 5.0 * 8.0 * registers_of(c) > 4.0e12) { msg = "mesh too large"; return false; }
   const double blk = (double)c->block[0] * c->block[1] * c->block[2] * 5.0;
   if (blk > 2.0e9) { msg = "MeshBlock too large"; return false; }
   return true;
@@ -188,8 +192,10 @@ std::vector<Plan> make_plans(hy_problem* const* ps, int32_t n) {
 }
 
 hy_status launch_group(hy_problem* const* ps, const std::vector<int>& act, const Plan& pl,
-                       int stage, const std::vector<int64_t>& step_of, int flags, hipStream_t s) {
-  // every problem in `act` has at least `stage` stages
+                       int stage, int kind, const std::vector<int64_t>& step_of, int flags,
+                       hipStream_t s) {
+  // every problem in `act` has at least `stage` stages, and that stage is of
+  // the given kernel kind (1: no step-start term, 2: with it)
   int tx, ty;
   stage_variant_shape(pl.variant, &tx, &ty);
   for (size_t c0 = 0; c0 < act.size(); c0 += kMaxBatch) {
@@ -216,7 +222,7 @@ hy_status launch_group(hy_problem* const* ps, const std::vector<int>& act, const
     if (tiles > 0x7fffffff) return fail(HY_ERR_ARG, "too many tiles in one launch");
     a.ntiles = (int32_t)tiles;
     if (tiles == 0) continue;
-    HY_HIP(launch_stage(pl.variant, pl.recon, pl.prec, stage == 1 ? 1 : 2, a, (int)tiles, s));
+    HY_HIP(launch_stage(pl.variant, pl.recon, pl.prec, kind, a, (int)tiles, s));
   }
   return HY_OK;
 }
@@ -247,6 +253,31 @@ hy_status launch_fix(hy_problem* const* ps, const std::vector<int>& act, const P
   return HY_OK;
 }
 
+// Pointwise steps between stages (RK1's copy, RK4's mix) for the problems
+// that need one after this stage.
+hy_status launch_combines(hy_problem* const* ps, const std::vector<int>& act, int stage,
+                          const std::vector<int64_t>& step_of, hipStream_t s) {
+  for (int op = 1; op <= 2; ++op) {
+    std::vector<int> f;
+    for (int q : act)
+      if (rk_combine_after(ps[q]->hp, stage) == op) f.push_back(q);
+    for (size_t c0 = 0; c0 < f.size(); c0 += kMaxBatch) {
+      FixArgs a;
+      std::memset(&a, 0, sizeof a);
+      int64_t most = 1;
+      for (size_t c = c0; c < std::min(f.size(), c0 + (size_t)kMaxBatch); ++c) {
+        FixEntry& e = a.e[a.nprob++];
+        e.p = ps[f[c]]->dp;
+        e.parity = (int32_t)(step_of[f[c]] & 1);
+        e.stage = stage;
+        most = std::max(most, ps[f[c]]->ncell * 5);
+      }
+      HY_HIP(launch_combine(a, op, (int)std::min<int64_t>((most + 255) / 256, 4096), s));
+    }
+  }
+  return HY_OK;
+}
+
 // Enqueue nsteps[q] steps of every problem; optional events around stages.
 hy_status run_batch(hy_problem* const* ps, const int32_t* nsteps, int32_t n, hipStream_t s,
                     std::vector<hipEvent_t>* ev, int flags) {
@@ -270,15 +301,22 @@ hy_status run_batch(hy_problem* const* ps, const int32_t* nsteps, int32_t n, hip
   for (int32_t k = 0; k < maxs; ++k) {
     for (int stage = 1; stage <= maxst; ++stage) {
       for (const Plan& pl : plans) {
-        std::vector<int> act;
+        std::vector<int> act, by_kind[2];
         for (int q : pl.idx)
-          if (nsteps[q] > k && ps[q]->hp.nstages >= stage) act.push_back(q);
-        st = launch_group(ps, act, pl, stage, step_of, flags, s);
-        if (st != HY_OK) return st;
+          if (nsteps[q] > k && ps[q]->hp.nstages >= stage) {
+            act.push_back(q);
+            by_kind[rk_stage_kind(ps[q]->hp, stage) - 1].push_back(q);
+          }
+        for (int kind = 1; kind <= 2; ++kind) {
+          st = launch_group(ps, by_kind[kind - 1], pl, stage, kind, step_of, flags, s);
+          if (st != HY_OK) return st;
+        }
         if (flags & 1) {  // FOFC belongs to counted (real) stages only
           st = launch_fix(ps, act, pl, stage, step_of, s);
           if (st != HY_OK) return st;
         }
+        st = launch_combines(ps, act, stage, step_of, s);
+        if (st != HY_OK) return st;
       }
       if (ev) HY_HIP(hipEventRecord((*ev)[evi++], s));
     }
@@ -347,7 +385,7 @@ size_t hy_workspace_bytes(const hy_config* cfg) {
     g_err = msg;
     return 0;
   }
-  return (size_t)kHeaderBytes + (size_t)stages_of(cfg) * reg_bytes(cfg) + flag_bytes(cfg);
+  return (size_t)kHeaderBytes + (size_t)registers_of(cfg) * reg_bytes(cfg) + flag_bytes(cfg);
 }
 
 hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_problem** out) {
@@ -407,34 +445,12 @@ hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_prob
   h.rho_floor = cfg->rho_floor;
   h.p_floor = cfg->p_floor;
   h.fofc = cfg->fofc;
-  const int nst = stages_of(cfg);
-  h.W = nst == 3 ? (double*)(p->ws + kHeaderBytes + 2 * reg_bytes(cfg)) : nullptr;
-  h.flags = cfg->fofc ? (uint8_t*)(p->ws + kHeaderBytes + (size_t)nst * reg_bytes(cfg)) : nullptr;
+  const int nreg = registers_of(cfg);
+  h.W = nreg == 3 ? (double*)(p->ws + kHeaderBytes + 2 * reg_bytes(cfg)) : nullptr;
+  h.flags = cfg->fofc ? (uint8_t*)(p->ws + kHeaderBytes + (size_t)nreg * reg_bytes(cfg)) : nullptr;
   h.fofc_cnt = p->dc->fofc_cnt;
   h.fofc_total = &p->dc->fofc_total;
-  // low-storage SSP-RK stages: dst = a U + b src + c dt L(src)
-  h.nstages = nst;
-  h.src[0] = h.U;
-  h.dst[0] = h.V;
-  h.rk_a[0] = 0.0;
-  h.rk_b[0] = 1.0;
-  h.rk_c[0] = 1.0;
-  if (nst == 2) {  // SSPRK(2,2)
-    h.src[1] = h.V;
-    h.dst[1] = h.U;
-    h.rk_a[1] = h.rk_b[1] = h.rk_c[1] = 0.5;
-  } else {         // SSPRK(3,3) of Shu & Osher
-    h.src[1] = h.V;
-    h.dst[1] = h.W;
-    h.rk_a[1] = 0.75;
-    h.rk_b[1] = 0.25;
-    h.rk_c[1] = 0.25;
-    h.src[2] = h.W;
-    h.dst[2] = h.U;
-    h.rk_a[2] = 1.0 / 3.0;
-    h.rk_b[2] = 2.0 / 3.0;
-    h.rk_c[2] = 2.0 / 3.0;
-  }
+  h.nstages = stages_of(cfg);  // registers and weights per stage: rk_stage_of()
 
   unsigned char hdr[kHeaderBytes];
   std::memset(hdr, 0, sizeof hdr);
@@ -466,6 +482,7 @@ hy_status hy_set_state(hy_problem* p, const double* U, int where, void* stream) 
   }
   HY_HIP(launch_scatter(p->dp, src, p->hp.U, p->ncell * 5, 1, s));
   const int slot = (int)(p->steps & 1);
+  HY_HIP(launch_reset(p->dp, slot ^ 1, 0, s));  // the slot the next step reduces into
   HY_HIP(launch_reset(p->dp, slot, 1, s));
   HY_HIP(launch_dt(p->dp, p->ncell, slot, 1, s));
   if (where == HY_HOST) HY_HIP(hipStreamSynchronize(s));
@@ -661,10 +678,11 @@ hy_status hy_autotune(hy_problem* p, void* stream, int32_t full_steps, int32_t* 
         int32_t n = full_steps;
         st = run_batch(ps, &n, 1, s, nullptr, 1);
       } else {
-        st = launch_group(ps, act, pl, 1, step_of, 0, s);  // warm-up
+        st = launch_group(ps, act, pl, 1, 1, step_of, 0, s);  // warm-up
         if (st != HY_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) { st = fail(HY_ERR_HIP, "event record"); break; }
-        for (int r = 0; r < reps && st == HY_OK; ++r) st = launch_group(ps, act, pl, 1, step_of, 0, s);
+        for (int r = 0; r < reps && st == HY_OK; ++r)
+          st = launch_group(ps, act, pl, 1, 1, step_of, 0, s);
       }
       if (st != HY_OK) break;
       if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {

@@ -37,14 +37,60 @@ struct DevProblem {
   unsigned long long* fofc_cnt;  // [2] cells flagged in the stages of sequence parity 0/1
   unsigned long long* fofc_total;
   int32_t fofc;              // 1: first-order flux correction enabled
-  // Low-storage SSP-RK stage s (1-based) forms
-  //   dst[s-1] = a[s-1] U + b[s-1] src[s-1] + c[s-1] dt L(src[s-1])
-  // (stage 1 has a = 0, b = c = 1 and is evaluated as src + dt L).
-  int32_t nstages;           // 2 or 3
-  const double* src[3];
-  double* dst[3];
-  double rk_a[3], rk_b[3], rk_c[3];
+  int32_t nstages;           // SSP-RK stages per step: 1, 2, 3 or 10 (RK4)
 };
+
+// One low-storage SSP-RK stage: dst = a U + b src + c dt L(src), evaluated as
+// src + c dt L(src) when a == 0 (the "first" kind of stage kernel).
+struct RkStage {
+  const double* src;
+  double* dst;
+  double a, b, c;
+};
+
+// The stage table (Sec. 3: low-storage SSP-RK of the Ketcheson family).
+//  RK1: U -> V, then V is copied to U.
+//  RK2 SSPRK(2,2): U -> V (0, 1, 1); V -> U (1/2, 1/2, 1/2).
+//  RK3 SSPRK(3,3): U -> V (0, 1, 1); V -> W (3/4, 1/4, 1/4);
+//                  W -> U (1/3, 2/3, 2/3).
+//  RK4 SSPRK(10,4): U keeps q2; q1 runs U -> V -> W -> V ... through stages
+//  1-9 as q1 + dt/6 L(q1); after stage 5 (q1 in V) U <- U/25 + 9 V/25 and
+//  V <- 15 U - 5 V; stage 10: V -> U with (1, 3/5, 1/10).
+__host__ __device__ inline RkStage rk_stage_of(const DevProblem& P, int stage) {
+  RkStage s{P.U, P.V, 0.0, 1.0, 1.0};
+  if (P.nstages == 2) {
+    if (stage == 2) s = RkStage{P.V, P.U, 0.5, 0.5, 0.5};
+  } else if (P.nstages == 3) {
+    if (stage == 2) s = RkStage{P.V, P.W, 0.75, 0.25, 0.25};
+    if (stage == 3) s = RkStage{P.W, P.U, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0};
+  } else if (P.nstages == 10) {
+    if (stage == 10) {
+      s = RkStage{P.V, P.U, 1.0, 3.0 / 5.0, 1.0 / 10.0};
+    } else {
+      s.c = 1.0 / 6.0;
+      if (stage > 1) {
+        s.src = (stage & 1) ? P.W : P.V;
+        s.dst = (stage & 1) ? P.V : P.W;
+      }
+    }
+  }
+  return s;
+}
+
+// Pointwise step after a stage: 1 copies V to U (RK1, after its stage);
+// 2 is the RK4 mix after stage 5. 0: none.
+__host__ __device__ inline int rk_combine_after(const DevProblem& P, int stage) {
+  if (P.nstages == 1 && stage == 1) return 1;
+  if (P.nstages == 10 && stage == 5) return 2;
+  return 0;
+}
+
+// Stage-kernel kind: 1 for a stage with no step-start term that is not the
+// last one, 2 otherwise (the last stage of a step also reduces the next time
+// step; with a == 0, b == 1 its update equals the kind-1 one exactly).
+__host__ __device__ inline int rk_stage_kind(const DevProblem& P, int stage) {
+  return rk_stage_of(P, stage).a == 0.0 && stage != P.nstages ? 1 : 2;
+}
 
 // Counters that follow the descriptor in the header.
 struct DevCounters {

@@ -538,12 +538,24 @@ __device__ __forceinline__ void face_flux(const Gas<T>& gas, const T* __restrict
 }
 
 // -------------------------------------------------------------- the stage
-// STAGE 1 (first RK stage): dst = src + dt L(src), with src the step-start
-// state U. STAGE 2 (later stages): dst = a U + b src + c dt L(src). RK2:
-// V = U + dt L(U), then U = U/2 + V/2 + dt L(V)/2. RK3: V = U + dt L(U),
-// W = 3U/4 + V/4 + dt L(V)/4, U = U/3 + 2W/3 + 2 dt L(W)/3. The last stage of
-// a problem also reduces the minimum of dx_d/lambda_d over its new U for the
-// next time step.
+// A pointer that is the same in every lane, moved to scalar registers. The
+// compiler cannot always prove the register choice of rk_stage_of uniform and
+// otherwise keeps both pointers in vector registers, which costs spills in
+// the larger variants.
+template <typename P>
+__device__ __forceinline__ P* uniform_ptr(P* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (P*)(((unsigned long long)hi << 32) | lo);
+}
+
+// STAGE 1 (stages without a step-start term, never a step's last):
+// dst = src + c dt L(src). STAGE 2 (the others): dst = a U + b src +
+// c dt L(src). Registers and weights come from rk_stage_of (RK2:
+// V = U + dt L(U), then U = U/2 + V/2 + dt L(V)/2; RK3 and RK4 in its
+// table). The last stage of a problem also reduces the minimum of
+// dx_d/lambda_d over its new state for the next time step.
 template <int RECON, typename T, int TX, int TY, int WPE, int STAGE>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_stage(const StageArgs a) {
@@ -592,11 +604,11 @@ k_stage(const StageArgs a) {
     const bool own = tx < nxv && ty < nyv;
     const int gi = i0 + tx, gj = j0 + ty;  // owned column, block-local
 
-    const int si = E.stage - 1;
-    const double* __restrict__ Sin = P.src[si];
-    double* __restrict__ Out = P.dst[si];
-    const double ca = P.rk_a[si], cb = P.rk_b[si], cc = P.rk_c[si];
-    const bool last = E.stage == P.nstages;  // uniform over the workgroup
+    const RkStage rs = rk_stage_of(P, E.stage);
+    const double* __restrict__ Sin = uniform_ptr(rs.src);
+    double* __restrict__ Out = uniform_ptr(rs.dst);
+    const double ca = rs.a, cb = rs.b, cc = rs.c;
+    const bool last = STAGE == 2 && E.stage == P.nstages;  // uniform over the workgroup
     const int64_t vs = geo.vstride;
 
     const double gamma = P.gamma, gm1 = gamma - 1.0;
@@ -606,7 +618,9 @@ k_stage(const StageArgs a) {
     const double idx = 1.0 / P.dx[0], idy = 1.0 / P.dx[1], idz = 1.0 / P.dx[2];
     const bool count = (E.flags & 1) != 0;
 
-    if (STAGE == 1 && loc == 0 && tid == 0) P.dtmin[E.parity ^ 1] = kInfBits;
+    // the slot this step reduces into; a one-stage step has no earlier
+    // launch to clear it, so the copy that ends its previous step does
+    if (E.stage == 1 && P.nstages > 1 && loc == 0 && tid == 0) P.dtmin[E.parity ^ 1] = kInfBits;
     const bool fofc = P.fofc && count;
     if (fofc && loc == 0 && tid == 0) {  // fold the counter of two stages ago
       *P.fofc_total = *P.fofc_total + P.fofc_cnt[(E.seq + 1) & 1];
@@ -914,7 +928,7 @@ k_stage(const StageArgs a) {
           l -= (fyp - fym) * idy;
           l -= (fz[v] - zq.fm[v]) * idz;
           if (STAGE == 1) {
-            unew[v] = uc[v] + dt * l;
+            unew[v] = uc[v] + (cc * dt) * l;
           } else {
             unew[v] = (ca * un0[v] + cb * uc[v]) + (cc * dt) * l;
           }
@@ -937,7 +951,7 @@ k_stage(const StageArgs a) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(unew[v], Out + off + v * vs);
         }
-        if (STAGE == 2 && last) mydt = fmin(mydt, cell_dt(fl, gamma, gm1, P.dx, unew));
+        if (last) mydt = fmin(mydt, cell_dt(fl, gamma, gm1, P.dx, unew));
       }
     }
 
@@ -946,7 +960,7 @@ k_stage(const StageArgs a) {
       if (hits) atomicAdd(P.floor_hits, (unsigned long long)hits);
       if (bad) atomicOr(P.err, 1u);
     }
-    if (STAGE == 2 && last) {
+    if (last) {
       unsigned long long b = (unsigned long long)__double_as_longlong(mydt);
 #pragma unroll
       for (int s = kWave / 2; s > 0; s >>= 1) {
@@ -1065,15 +1079,15 @@ __global__ void __launch_bounds__(256) k_fofc_fix(const FixArgs a) {
   const FixEntry E = a.e[blockIdx.y];
   const DevProblem& P = *E.p;
   if (P.fofc_cnt[E.seq & 1] == 0ull) return;
-  const int si = E.stage - 1;
+  const RkStage rs = rk_stage_of(P, E.stage);
   if (E.last && blockIdx.x == 0 && threadIdx.x == 0) P.dtmin[E.parity ^ 1] = kInfBits;
-  const double* __restrict__ S = P.src[si];
-  double* Out = P.dst[si];  // is P.U itself in a problem's last stage
+  const double* __restrict__ S = rs.src;
+  double* Out = rs.dst;  // is P.U itself in a problem's last stage (not for RK1)
   const double gamma = P.gamma, gm1 = gamma - 1.0;
   const Gas<T> gas{T(gamma), T(gm1), T((gamma + 1.0) / (2.0 * gamma))};
   const Floors fl{P.rho_floor, P.p_floor / gm1};
   const double dt = P.cfl * __longlong_as_double((long long)P.dtmin[E.parity]);
-  const double cst = P.rk_c[si] * dt;
+  const double cst = rs.c * dt;
   const double id[3] = {1.0 / P.dx[0], 1.0 / P.dx[1], 1.0 / P.dx[2]};
   const int slabs = (P.bz + kFixPlanes - 1) / kFixPlanes;
   for (int w = blockIdx.x; w < P.nblocks * slabs; w += gridDim.x) {
@@ -1112,16 +1126,15 @@ __global__ void __launch_bounds__(256) k_fofc_fix(const FixArgs a) {
         }
         double us[5], unew[5];
         load5(S, off, geo.vstride, us);
-        if (si == 0) {
+        if (rs.a == 0.0) {
 #pragma unroll
-          for (int v = 0; v < 5; ++v) unew[v] = us[v] + dt * l[v];
+          for (int v = 0; v < 5; ++v) unew[v] = us[v] + (rs.c * dt) * l[v];
         } else {
           double u0[5];
 #pragma unroll
           for (int v = 0; v < 5; ++v) u0[v] = P.U[off + v * geo.vstride];
-          const double ca = P.rk_a[si], cb = P.rk_b[si], cc = P.rk_c[si];
 #pragma unroll
-          for (int v = 0; v < 5; ++v) unew[v] = (ca * u0[v] + cb * us[v]) + (cc * dt) * l[v];
+          for (int v = 0; v < 5; ++v) unew[v] = (rs.a * u0[v] + rs.b * us[v]) + (rs.c * dt) * l[v];
         }
 #pragma unroll
         for (int v = 0; v < 5; ++v) Out[off + v * geo.vstride] = unew[v];
@@ -1154,12 +1167,13 @@ __global__ void __launch_bounds__(256) k_fofc_dt(const FixArgs a) {
   const double gamma = P.gamma, gm1 = gamma - 1.0;
   const Floors fl{P.rho_floor, P.p_floor / gm1};
   const int64_t ncell = (int64_t)P.nblocks * P.vstride;
+  const double* __restrict__ Un = rk_stage_of(P, P.nstages).dst;  // the new state
   double mydt = __longlong_as_double((long long)kInfBits);
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x) {
     const int64_t m = c / P.vstride, rr = c - m * P.vstride;
     double u[5];
-    load5c(P.U, m * P.bstride + rr, P.vstride, u);
+    load5c(Un, m * P.bstride + rr, P.vstride, u);
     mydt = fmin(mydt, cell_dt(fl, gamma, gm1, P.dx, u));
   }
   unsigned long long b = (unsigned long long)__double_as_longlong(mydt);
@@ -1174,6 +1188,28 @@ __global__ void __launch_bounds__(256) k_fofc_dt(const FixArgs a) {
     unsigned long long mn = red[0];
     for (int w = 1; w < 4; ++w) mn = red[w] < mn ? red[w] : mn;
     atomicMin(P.dtmin + (E.parity ^ 1), mn);
+  }
+}
+
+// Pointwise step between RK stages (rk_combine_after): op 1 copies V to U
+// (RK1), op 2 is the SSPRK(10,4) mix after stage 5, U <- U/25 + 9 V/25, then
+// V <- 15 U - 5 V, element by element. Op 1 ends a one-stage step: it also
+// clears the time-step slot this step read, which the next step reduces into.
+__global__ void __launch_bounds__(256) k_combine(const FixArgs a, int op) {
+  const FixEntry E = a.e[blockIdx.y];
+  const DevProblem& P = *E.p;
+  if (op == 1 && blockIdx.x == 0 && threadIdx.x == 0) P.dtmin[E.parity] = kInfBits;
+  const int64_t n = (int64_t)P.nblocks * P.bstride;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = P.V[i];
+    if (op == 1) {
+      P.U[i] = v;
+    } else {
+      const double u = P.U[i] / 25.0 + 9.0 / 25.0 * v;
+      P.U[i] = u;
+      P.V[i] = 15.0 * u - 5.0 * v;
+    }
   }
 }
 
@@ -1317,6 +1353,11 @@ hipError_t launch_fofc(int recon, int prec, const FixArgs& a, int grid_x, hipStr
 }
 
 int fofc_grid(int nblocks, int bz) { return nblocks * ((bz + kFixPlanes - 1) / kFixPlanes); }
+
+hipError_t launch_combine(const FixArgs& a, int op, int grid_x, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, dim3(grid_x, a.nprob), dim3(256), 0, s, a, op);
+  return hipGetLastError();
+}
 
 hipError_t launch_reset(const DevProblem* p, int slot, int clear, hipStream_t s) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, p, slot, clear);

@@ -11,6 +11,7 @@ hipError_t launch_stage(int v, int recon, int prec, int stage, const StageArgs& 
                         hipStream_t s);
 hipError_t launch_fofc(int recon, int prec, const FixArgs& a, int grid_x, hipStream_t s);
 int fofc_grid(int nblocks, int bz);
+hipError_t launch_combine(const FixArgs& a, int op, int grid_x, hipStream_t s);
 hipError_t launch_reset(const DevProblem* p, int slot, int clear, hipStream_t s);
 hipError_t launch_dt(const DevProblem* p, int64_t ncell, int slot, int flags, hipStream_t s);
 hipError_t launch_scatter(const DevProblem* p, const double* src, double* dst, int64_t n,

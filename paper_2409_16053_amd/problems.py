@@ -55,7 +55,7 @@ class Problem:
     rho_floor: float = 1e-10
     p_floor: float = 1e-13
     fofc: int = 0                 # first-order flux correction (Sec. 3) on/off
-    rk: int = 2                   # SSP-RK stages (Sec. 3): 1, 2 or 3
+    rk: int = 2                   # SSP-RK order (Sec. 3): 1, 2, 3 or 4 (SSPRK(10,4))
     name: str = ""
     meta: dict = field(default_factory=dict)
 

@@ -1,5 +1,6 @@
 """GPU parity of the higher-order options: WENO-Z and PPMX reconstruction
-and the three-stage SSP-RK integrator, against the CPU reference solver.
+and the one-, three- and ten-stage SSP-RK integrators (RK1, RK3 and the
+fourth-order SSPRK(10,4)), against the CPU reference solver.
 
 FP64 gate: rel L1 <= 1e-12 and per-variable elementwise agreement <= 1e-9 of
 the variable's largest magnitude; mixed precision: rel L1 <= 1e-5 against the
@@ -61,7 +62,8 @@ def _check(hy, pb, steps, label, **kw):
 
 
 @pytest.mark.parametrize("recon,rk", [(P.WENOZ, 3), (P.WENOZ, 2), (P.PLM, 3), (P.PPM4, 3), (P.PPMX, 3),
-                                     (P.PPMX, 2)])
+                                     (P.PPMX, 2), (P.WENOZ, 4), (P.PLM, 4), (P.PPMX, 4),
+                                     (P.PLM, 1), (P.WENOZ, 1)])
 def test_turbulence_schemes(hy, recon, rk):
     pb = P.turbulence(N=48, seed=3, kmax=8).with_(block=(16, 16, 24), recon=recon, rk=rk)
     _check(hy, pb, 8, f"turb {recon}/{rk}")
@@ -103,12 +105,21 @@ def test_sedov_outflow_wenoz_rk3(hy):
     _check(hy, pb, 12, "sedov wenoz")
 
 
-@pytest.mark.parametrize("recon", [P.WENOZ, P.PPM4, P.PPMX])
-def test_fofc_hypersonic_rk3(hy, recon):
-    pb = P.turbulence(N=32, seed=5, kmax=8, mach=20).with_(block=(16, 16, 16), recon=recon, rk=3,
+@pytest.mark.parametrize("recon,rk", [(P.WENOZ, 3), (P.PPM4, 3), (P.PPMX, 3), (P.WENOZ, 4),
+                                     (P.PLM, 4), (P.PLM, 1), (P.PPM4, 1)])
+def test_fofc_hypersonic_rk3(hy, recon, rk):
+    pb = P.turbulence(N=32, seed=5, kmax=8, mach=20).with_(block=(16, 16, 16), recon=recon, rk=rk,
                                                            fofc=1)
-    U, q, ref = _check(hy, pb, 12, f"fofc rk3 {recon}")
+    U, q, ref = _check(hy, pb, 12, f"fofc rk{rk} {recon}")
     assert ref["fofc_cells"] > 0
+
+
+@pytest.mark.parametrize("rk", [1, 4])
+def test_sod_rk1_rk4(hy, rk):
+    # the mix after stage 5 and the V -> U copy of RK1 run between stages:
+    # a discontinuity across several blocks checks their indexing
+    pb = P.sod(N=64, axis=1, ntrans=8).with_(block=(8, 32, 8), recon=P.PLM, rk=rk)
+    _check(hy, pb, 15, f"sod rk{rk}")
 
 
 @pytest.mark.parametrize("recon,order", [(P.WENOZ, 4.5), (P.PPMX, 3.8)])
@@ -149,7 +160,7 @@ def test_mixed_rk3_vs_fp64_reference(hy, case):
         # break keeps it at 1e-7
         noise = 1e-3 if recon == P.WENOZ else 1e-6
         pb, steps = P.sedov(N=32, seed=3, noise=noise).with_(block=(16, 16, 16)), 20
-    pb = pb.with_(recon=recon, rk=3)
+    pb = pb.with_(recon=recon, rk=4 if case == "turb_wenoz" else 3)
     ref = oracle.advance(pb, steps)
     U, _ = _run(hy, pb.with_(precision=P.MIXED), steps)
     r = _rel(U, ref["U"])
@@ -168,12 +179,18 @@ def test_rk3_every_tile_shape_bitwise(hy, recon):
 
 @pytest.mark.parametrize("recon", [P.PLM, P.PPM4, P.WENOZ, P.PPMX])
 @pytest.mark.parametrize("prec", [P.FP64, P.MIXED])
-def test_uniform_state_rk3(hy, recon, prec):
+@pytest.mark.parametrize("rk", [1, 3, 4])
+def test_uniform_state_rk3(hy, recon, prec, rk):
+    # the weights of RK3 and RK4 are not all exact in binary: a few ulps per
+    # stage, the same bound the reference solver's own pin uses
     pb = P.uniform(n=(32, 24, 16), rho=1.3, v=(0.3, -0.2, 0.4), p=0.8, bc=P.PERIODIC)
-    pb = pb.with_(block=(16, 8, 8), recon=recon, precision=prec, rk=3)
+    pb = pb.with_(block=(16, 8, 8), recon=recon, precision=prec, rk=rk)
     U, q = _run(hy, pb, 3)
+    nst = {1: 1, 3: 3, 4: 10}[rk]
     ulp = np.spacing(np.abs(pb.U))
-    assert np.all(np.abs(U - pb.U) <= 2 * 3 * 3 * ulp)
+    assert np.all(np.abs(U - pb.U) <= 4 * nst * 3 * ulp)
+    if rk == 1:
+        assert np.array_equal(U, pb.U)
     assert q["floor_hits"] == 0
 
 
@@ -183,8 +200,11 @@ def test_batch_mixing_integrators_equals_alone(hy):
            P.sedov(N=32, seed=23).with_(block=(32, 32, 32), rk=3),
            P.sedov(N=32, seed=24).with_(block=(32, 32, 32)),
            P.kelvin_helmholtz(N=32, seed=25).with_(block=(16, 16, 16), recon=P.PPM4, rk=3,
-                                                   precision=P.MIXED)]
-    steps = [5, 7, 4, 6, 3]
+                                                   precision=P.MIXED),
+           P.turbulence(N=32, seed=27, kmax=8).with_(block=(16, 16, 16), recon=P.WENOZ, rk=4),
+           P.turbulence(N=32, seed=28, kmax=8, mach=20).with_(block=(16, 16, 16), rk=1, fofc=1),
+           P.sedov(N=32, seed=29).with_(block=(16, 32, 16), rk=4, fofc=1)]
+    steps = [5, 7, 4, 6, 3, 2, 6, 3]
     alone = [_run(hy, pb, n) for pb, n in zip(pbs, steps)]
     gs = [hy.Problem(pb).set_state() for pb in pbs]
     hy.batch_advance(gs, steps)
@@ -195,16 +215,23 @@ def test_batch_mixing_integrators_equals_alone(hy):
         g.close()
 
 
-def test_graph_replay_rk3(hy):
+@pytest.mark.parametrize("rk", [1, 3, 4])
+def test_graph_replay_rk3(hy, rk):
     import torch
-    pb = P.turbulence(N=32, seed=26, kmax=8).with_(block=(16, 16, 16), recon=P.WENOZ, rk=3, fofc=1)
-    ref, _ = _run(hy, pb, 6)
+    # RK1 and RK4 at Mach 20 so that the flux correction also replays
+    extra = {} if rk == 3 else {"mach": 20}
+    pb = P.turbulence(N=32, seed=26, kmax=8, **extra).with_(block=(16, 16, 16), recon=P.WENOZ,
+                                                           rk=rk, fofc=1)
+    ref, qref = _run(hy, pb, 6)
     g = hy.Problem(pb).set_state()
     s = torch.cuda.Stream()
-    for _ in range(3):
+    for r in range(3):  # replays with eager copies and synchronisations between them
         hy.batch_advance_graph([g], [2], stream=s)
         s.synchronize()
+        assert g.query()["steps"] == 2 * (r + 1)
+    q = g.query()
     assert np.array_equal(g.get_state(), ref)
+    assert q["dt"] == qref["dt"] and q["t"] == qref["t"] and q["fofc_cells"] == qref["fofc_cells"]
     g.close()
 
 
@@ -213,5 +240,8 @@ def test_workspace_has_third_register(hy):
     n2 = hy.workspace_bytes(pb)
     n3 = hy.workspace_bytes(pb.with_(rk=3))
     assert n3 - n2 == (16 ** 3 * 5 * 8 + 255) // 256 * 256
-    with pytest.raises(hy.HydroError):
-        hy.workspace_bytes(pb.with_(rk=4))
+    assert hy.workspace_bytes(pb.with_(rk=4)) == n3  # SSPRK(10,4) is low-storage: 3 registers
+    assert hy.workspace_bytes(pb.with_(rk=1)) == n2
+    for bad in (-1, 5):
+        with pytest.raises(hy.HydroError):
+            hy.workspace_bytes(pb.with_(rk=bad))
