@@ -428,11 +428,12 @@ def run_serving_workload(hy, P, count, budgets_gb, seed=4, epoch=10):
     steps, FP64 or mixed), admitted by an HBM budget: continuous batching
     against one request at a time. Initial states are generated before the
     runs; the arrival rate is 0.8 / (mean service time of the one-at-a-time
-    path over the first requests, all queued at once)."""
+    path over all the requests, all queued at once), so the offered load is
+    80% of what that path can serve."""
     from paper_2409_16053_amd import serve
     log(f"serving: generating {count} initial states")
     inputs = serve.generate_inputs(seed, count)
-    calib = min(count, 30)
+    calib = count
     probe = serve.make_stream(seed, calib, rate=1e9, inputs=inputs)
     t0 = time.perf_counter()
     serve.run_fifo(probe, keep="none", client_threads=16)
@@ -453,6 +454,7 @@ def run_serving_workload(hy, P, count, budgets_gb, seed=4, epoch=10):
                      "peak_resident_gb": srv.peak_bytes / 2 ** 30, "epochs": srv.epochs,
                      "results_equal_alone": bool(all(a.digest == b.digest for a, b in zip(cont, fifo)))})
     out = {"requests": count, "rate_per_s": rate, "mean_service_ms_one_at_a_time": mean_service * 1e3,
+           "calibration_requests": calib,
            "epoch_steps": epoch, "fifo": sf}
     out.update(runs[0])
     if len(runs) > 1:

@@ -102,7 +102,7 @@ typedef struct {
 /* Device bytes one problem needs (the MeshBlockPack of Sec. 2, "Data
  * locality", with no stored ghost cells): two FP64 state registers of
  * 5 x cells doubles each (the step-start state and the RK stage state; three
- * with rk = 3 or 4), a 512-byte header, and with fofc one byte of flag per
+ * with rk = 3 or 4), a 1024-byte header, and with fofc one byte of flag per
  * cell.
  * Returns 0 for an invalid configuration (message in hy_last_error). */
 size_t hy_workspace_bytes(const hy_config* cfg);
@@ -202,11 +202,11 @@ hy_status hy_get_launch(const hy_problem* p, int32_t* variant, int32_t* kc);
 
 /* Time every compiled tile shape and a few z-chunk lengths on this problem's
  * own state, keep the fastest for this problem and cache it for its (block
- * size, recon, precision) class. With full_steps == 0 only stage-1 launches
- * are timed, which leave the state unchanged; with full_steps > 0 each
- * candidate runs that many complete RK steps (FOFC and counters included)
- * after one warm-up step, which ADVANCES the state (tune a scratch copy).
- * Synchronous. Returns the chosen
+ * size, recon, precision) class. Each candidate is timed three times and its
+ * best time kept. With full_steps == 0 only stage-1 launches are timed, which
+ * leave the state unchanged; with full_steps > 0 each timing runs that many
+ * complete RK steps (FOFC and counters included), after one warm-up step,
+ * which ADVANCES the state (tune a scratch copy). Synchronous. Returns the chosen
  * shape in *variant/*kc (either may be NULL) and its time per stage in
  * *us_per_stage. */
 hy_status hy_autotune(hy_problem* p, void* hip_stream, int32_t full_steps, int32_t* variant,

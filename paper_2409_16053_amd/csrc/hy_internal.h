@@ -12,9 +12,19 @@
 
 namespace hy {
 
-constexpr int kHeaderBytes = 512;
+constexpr int kHeaderBytes = 1024;
 constexpr int kMaxBatch = 48;   // problems per launch (kernel-argument budget)
 constexpr int kWave = 64;       // CDNA wavefront width
+
+// One low-storage SSP-RK stage: dst = a U + b src + c dt L(src), evaluated as
+// src + c dt L(src) when a == 0 (the "first" kind of stage kernel).
+struct RkStage {
+  const double* src;
+  double* dst;
+  double a, b, c;
+};
+
+constexpr int kMaxStages = 10;  // SSPRK(10,4)
 
 // Per-problem descriptor in device memory (first bytes of the workspace).
 struct DevProblem {
@@ -38,14 +48,7 @@ struct DevProblem {
   unsigned long long* fofc_total;
   int32_t fofc;              // 1: first-order flux correction enabled
   int32_t nstages;           // SSP-RK stages per step: 1, 2, 3 or 10 (RK4)
-};
-
-// One low-storage SSP-RK stage: dst = a U + b src + c dt L(src), evaluated as
-// src + c dt L(src) when a == 0 (the "first" kind of stage kernel).
-struct RkStage {
-  const double* src;
-  double* dst;
-  double a, b, c;
+  RkStage rk[kMaxStages];    // rk_stage_of(*this, s) at [s - 1], filled at creation
 };
 
 // The stage table (Sec. 3: low-storage SSP-RK of the Ketcheson family).
@@ -56,6 +59,8 @@ struct RkStage {
 //  RK4 SSPRK(10,4): U keeps q2; q1 runs U -> V -> W -> V ... through stages
 //  1-9 as q1 + dt/6 L(q1); after stage 5 (q1 in V) U <- U/25 + 9 V/25 and
 //  V <- 15 U - 5 V; stage 10: V -> U with (1, 3/5, 1/10).
+// Kernels read the copy in DevProblem::rk: a table load schedules better than
+// this chain of selects.
 __host__ __device__ inline RkStage rk_stage_of(const DevProblem& P, int stage) {
   RkStage s{P.U, P.V, 0.0, 1.0, 1.0};
   if (P.nstages == 2) {

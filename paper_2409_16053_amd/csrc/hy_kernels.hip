@@ -539,9 +539,10 @@ __device__ __forceinline__ void face_flux(const Gas<T>& gas, const T* __restrict
 
 // -------------------------------------------------------------- the stage
 // A pointer that is the same in every lane, moved to scalar registers. The
-// compiler cannot always prove the register choice of rk_stage_of uniform and
-// otherwise keeps both pointers in vector registers, which costs spills in
-// the larger variants.
+// compiler does not prove the stage's register pointers uniform (they come
+// from a table indexed by the batch entry) and otherwise keeps them in vector
+// registers, which costs registers, spills in the larger variants and a
+// looser load schedule.
 template <typename P>
 __device__ __forceinline__ P* uniform_ptr(P* p) {
   const unsigned long long v = (unsigned long long)p;
@@ -604,9 +605,10 @@ k_stage(const StageArgs a) {
     const bool own = tx < nxv && ty < nyv;
     const int gi = i0 + tx, gj = j0 + ty;  // owned column, block-local
 
-    const RkStage rs = rk_stage_of(P, E.stage);
+    const RkStage& rs = P.rk[E.stage - 1];
     const double* __restrict__ Sin = uniform_ptr(rs.src);
     double* __restrict__ Out = uniform_ptr(rs.dst);
+    const double* __restrict__ U0 = uniform_ptr((const double*)P.U);
     const double ca = rs.a, cb = rs.b, cc = rs.c;
     const bool last = STAGE == 2 && E.stage == P.nstages;  // uniform over the workgroup
     const int64_t vs = geo.vstride;
@@ -918,7 +920,7 @@ k_stage(const StageArgs a) {
         const int wy = NXF + ty * TX + tx;
         double uc[5], un0[5];
         load5c(Sin, off, vs, uc);
-        if (STAGE == 2) load5(P.U, off, vs, un0);
+        if (STAGE == 2) load5(U0, off, vs, un0);
         double unew[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -1079,7 +1081,7 @@ __global__ void __launch_bounds__(256) k_fofc_fix(const FixArgs a) {
   const FixEntry E = a.e[blockIdx.y];
   const DevProblem& P = *E.p;
   if (P.fofc_cnt[E.seq & 1] == 0ull) return;
-  const RkStage rs = rk_stage_of(P, E.stage);
+  const RkStage& rs = P.rk[E.stage - 1];
   if (E.last && blockIdx.x == 0 && threadIdx.x == 0) P.dtmin[E.parity ^ 1] = kInfBits;
   const double* __restrict__ S = rs.src;
   double* Out = rs.dst;  // is P.U itself in a problem's last stage (not for RK1)
@@ -1167,7 +1169,7 @@ __global__ void __launch_bounds__(256) k_fofc_dt(const FixArgs a) {
   const double gamma = P.gamma, gm1 = gamma - 1.0;
   const Floors fl{P.rho_floor, P.p_floor / gm1};
   const int64_t ncell = (int64_t)P.nblocks * P.vstride;
-  const double* __restrict__ Un = rk_stage_of(P, P.nstages).dst;  // the new state
+  const double* __restrict__ Un = P.rk[P.nstages - 1].dst;  // the new state
   double mydt = __longlong_as_double((long long)kInfBits);
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x) {
