@@ -46,6 +46,25 @@ class Params(ctypes.Structure):
     ]
 
 
+class Smr(ctypes.Structure):
+    _fields_ = [
+        ("block", ctypes.c_int32 * 3),
+        ("lo", ctypes.c_int32 * 3),
+        ("hi", ctypes.c_int32 * 3),
+    ]
+
+
+def smr_params(pb) -> Smr:
+    """ctypes refinement block (block size and refined box) of a problem."""
+    S = Smr()
+    lo, hi = pb.refine if pb.refine is not None else ((0, 0, 0), (0, 0, 0))
+    for d in range(3):
+        S.block[d] = int(pb.block[d])
+        S.lo[d] = int(lo[d])
+        S.hi[d] = int(hi[d])
+    return S
+
+
 def _bind(L):
     dp = ctypes.POINTER(ctypes.c_double)
     pp = ctypes.POINTER(Params)
@@ -78,6 +97,17 @@ def _bind(L):
     L.or_set_threads.restype = None
     L.or_get_threads.argtypes = []
     L.or_get_threads.restype = ctypes.c_int
+    sp = ctypes.POINTER(Smr)
+    L.or_smr_leaves.argtypes = [pp, sp, ctypes.POINTER(ctypes.c_int32)]
+    L.or_smr_leaves.restype = ctypes.c_int
+    L.or_smr_new_dt.argtypes = [pp, sp, dp]
+    L.or_smr_new_dt.restype = ctypes.c_double
+    L.or_smr_advance.argtypes = [pp, sp, dp, ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_longlong)]
+    L.or_smr_advance.restype = ctypes.c_int
+    L.or_smr_fill_ghosts.argtypes = [pp, sp, dp, dp]
+    L.or_smr_fill_ghosts.restype = ctypes.c_int
+    L.or_smr_divergence.argtypes = [pp, sp, dp, dp, ctypes.POINTER(ctypes.c_longlong)]
+    L.or_smr_divergence.restype = ctypes.c_int
     return L
 
 
@@ -136,7 +166,43 @@ class Oracle:
         """CFL time step of a state (Sec. 3, Eq. 3)."""
         U = np.ascontiguousarray(pb.U if U is None else U, dtype=np.float64)
         P = params(pb)
+        if pb.refine is not None:
+            S = smr_params(pb)
+            return float(self._L.or_smr_new_dt(ctypes.byref(P), ctypes.byref(S), _dp(U)))
         return float(self._L.or_new_dt(ctypes.byref(P), _dp(U)))
+
+    def smr_leaves(self, pb):
+        """Leaves of a refined mesh as int32 [leaf][level, lx, ly, lz]."""
+        P, S = params(pb), smr_params(pb)
+        n = self._L.or_smr_leaves(ctypes.byref(P), ctypes.byref(S), None)
+        if n < 0:
+            raise ValueError(f"bad refined mesh (status {-n})")
+        out = np.zeros((n, 4), dtype=np.int32)
+        self._L.or_smr_leaves(ctypes.byref(P), ctypes.byref(S),
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        return out
+
+    def smr_fill_ghosts(self, pb, U=None):
+        """Ghosted leaves [leaf][5][bz+2g][by+2g][bx+2g]: face ghosts from the
+        level representation, edges and corners 0."""
+        U = np.ascontiguousarray(pb.U if U is None else U, dtype=np.float64)
+        g = self._L.or_nghost(int(pb.recon))
+        bx, by, bz = pb.block
+        out = np.zeros((U.shape[0], 5, bz + 2 * g, by + 2 * g, bx + 2 * g))
+        P, S = params(pb), smr_params(pb)
+        st = self._L.or_smr_fill_ghosts(ctypes.byref(P), ctypes.byref(S), _dp(U), _dp(out))
+        if st != OK:
+            raise ValueError(f"or_smr_fill_ghosts status {st}")
+        return out
+
+    def smr_divergence(self, pb, U=None):
+        U = np.ascontiguousarray(pb.U if U is None else U, dtype=np.float64)
+        L = np.empty_like(U)
+        P, S = params(pb), smr_params(pb)
+        fh = ctypes.c_longlong(0)
+        st = self._L.or_smr_divergence(ctypes.byref(P), ctypes.byref(S), _dp(U), _dp(L),
+                                       ctypes.byref(fh))
+        return L, st, fh.value
 
     def advance(self, pb, nsteps: int, U=None, t: float = 0.0, dt: float | None = None):
         """Run ``nsteps`` RK2 steps from state U (default ``pb.U``).
@@ -148,11 +214,17 @@ class Oracle:
         U = np.array(pb.U if U is None else U, dtype=np.float64, order="C", copy=True)
         P = params(pb)
         if dt is None:
-            dt = float(self._L.or_new_dt(ctypes.byref(P), _dp(U)))
+            dt = self.new_dt(pb, U)
         tt = ctypes.c_double(t)
         dd = ctypes.c_double(dt)
         fh = ctypes.c_longlong(0)
         fc = ctypes.c_longlong(0)
+        if pb.refine is not None:  # statically refined mesh, leaf-major U
+            S = smr_params(pb)
+            st = self._L.or_smr_advance(ctypes.byref(P), ctypes.byref(S), _dp(U), int(nsteps),
+                                        ctypes.byref(tt), ctypes.byref(dd), ctypes.byref(fh))
+            return dict(U=U, t=tt.value, dt=dd.value, floor_hits=fh.value, fofc_cells=0,
+                        status=st)
         st = self._L.or_advance(ctypes.byref(P), _dp(U), int(nsteps), ctypes.byref(tt),
                                 ctypes.byref(dd), ctypes.byref(fh), ctypes.byref(fc))
         return dict(U=U, t=tt.value, dt=dd.value, floor_hits=fh.value, fofc_cells=fc.value,
@@ -285,3 +357,15 @@ def hllc(gamma, wl, wr):
 
 def llf(gamma, wl, wr):
     return _inst().llf(gamma, wl, wr)
+
+
+def smr_leaves(pb):
+    return _inst().smr_leaves(pb)
+
+
+def smr_fill_ghosts(pb, U=None):
+    return _inst().smr_fill_ghosts(pb, U)
+
+
+def smr_divergence(pb, U=None):
+    return _inst().smr_divergence(pb, U)

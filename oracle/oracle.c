@@ -19,7 +19,9 @@
  *   -> CFL time step, Eq. 3: CFL times the minimum over all cells and all
  *      dimensions of dx_d / lambda_max,d.
  * It works on the whole mesh with no MeshBlock decomposition: splitting the
- * mesh into blocks changes no per-cell arithmetic.
+ * mesh into blocks changes no per-cell arithmetic. The or_smr_* functions at
+ * the end take a mesh with a statically refined box of blocks (two levels,
+ * Sec. 2); there each leaf block is ghost-filled and updated on its own.
  *
  * Readings where the paper is silent (each is listed with its reason in the
  * design notes): PLM uses the van Leer harmonic-mean limiter; PPM4 is
@@ -520,15 +522,14 @@ static void face_flux(const or_params* p, int d, const double wl[5], const doubl
 }
 
 static void flux_divergence(const or_params* p, work* w);
+static long long prims_and_fluxes(const or_params* p, work* w, int* bad);
 
 /* L(U) for the interior state Uin[5][nz][ny][nx]. Returns floor hits on
  * interior cells; sets *bad if any interior cell is unrecoverable. */
 static long long divergence(const or_params* p, work* w, const double* Uin, int* bad) {
   const grid* G = &w->G;
-  const int nx = p->n[0], ny = p->n[1], nz = p->n[2], g = G->g;
+  const int nx = p->n[0], ny = p->n[1], nz = p->n[2];
   const size_t nc = ncell(p);
-  long long hits = 0;
-  int anybad = 0;
 
   /* copy the interior into the ghosted array, then fill the ghosts */
   for (int v = 0; v < 5; ++v) {
@@ -538,6 +539,19 @@ static long long divergence(const or_params* p, work* w, const double* Uin, int*
         for (int i = 0; i < nx; ++i) w->U[at(G, v, i, j, k)] = Uin[v * nc + lin(p, i, j, k)];
   }
   fill_ghosts(p, G, w->U);
+  const long long hits = prims_and_fluxes(p, w, bad);
+  flux_divergence(p, w);
+  return hits;
+}
+
+/* Primitives on every stored cell of the ghosted w->U, then the face fluxes
+ * in x, y and z into w->F. Returns floor hits on interior cells; sets *bad
+ * if any interior cell is unrecoverable. */
+static long long prims_and_fluxes(const or_params* p, work* w, int* bad) {
+  const grid* G = &w->G;
+  const int nx = p->n[0], ny = p->n[1], nz = p->n[2], g = G->g;
+  long long hits = 0;
+  int anybad = 0;
 
   /* primitives on every stored cell */
 #pragma omp parallel for schedule(static) reduction(+ : hits) reduction(| : anybad)
@@ -569,8 +583,6 @@ static long long divergence(const or_params* p, work* w, const double* Uin, int*
           for (int v = 0; v < 5; ++v) w->F[d][(size_t)v * w->fsv[d] + ((size_t)k * fy + j) * fx + i] = f[v];
         }
   }
-
-  flux_divergence(p, w);
   if (bad) *bad = anybad;
   return hits;
 }
@@ -823,4 +835,419 @@ int or_fill_ghosts(const or_params* p, const double* Uin, double* Uout) {
         for (int i = 0; i < p->n[0]; ++i) Uout[at(&G, v, i, j, k)] = Uin[v * nc + lin(p, i, j, k)];
   fill_ghosts(p, &G, Uout);
   return OR_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Static mesh refinement (Sec. 2: the mesh is a tree of MeshBlocks that all
+ * hold the same number of cells; blocks that share a face differ by at most
+ * one level; ghost zones across a level change are filled by restriction or
+ * prolongation, and the flux through a face shared with finer blocks is
+ * replaced by the finer blocks' fluxes so that the update stays
+ * conservative).
+ *
+ * The mesh: root blocks of block[] cells tile the root grid p->n. The root
+ * blocks inside the box [lo, hi) (root-block units per axis) are refined once
+ * into 8 children of block[] cells at half the cell width (level 1). Leaves
+ * are ordered root by root, x fastest; a refined root contributes its
+ * children with the child's x offset fastest, then y, then z. The state is
+ * U[leaf][5][bz][by][bx], x fastest.
+ *
+ * The ghost cells of a leaf at level L hold the mesh's representation at
+ * level L, evaluated at the ghost cell's global index (indices outside the
+ * domain first follow the boundary condition at that level: periodic wrap,
+ * outflow clamp to the nearest interior cell):
+ *   level 0 at coarse cell I: the coarse leaf's cell when its root is not
+ *     refined; otherwise the mean of the 8 fine cells covering I, summed in
+ *     pairs along x, then y, then z, times 1/8 (restriction);
+ *   level 1 at fine cell i: the fine leaf's cell when its root is refined;
+ *     otherwise C + (sgn_x s_x + sgn_y s_y + sgn_z s_z)/4, with C the level-0
+ *     value at I = floor(i/2), s_d the minmod of the two level-0 differences
+ *     next to I along d (neighbours again by the boundary condition), and
+ *     sgn_d = +1 for the upper child (i odd), -1 for the lower (prolongation,
+ *     linear and limited; it conserves: the 8 children average to C).
+ * A coarse face shared with 4 fine faces takes the mean of their 4 fluxes,
+ * summed in pairs along the lower transverse axis first.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t block[3];  /* cells per block, even and >= 2 * ghosts per axis */
+  int32_t lo[3];     /* refined root blocks: lo <= root index < hi per axis */
+  int32_t hi[3];     /* (no refinement when the box is empty)             */
+} or_smr;
+
+typedef struct {
+  or_params p;   /* the root grid */
+  int b[3];      /* cells per block */
+  int nr[3];     /* root blocks per axis */
+  int nroot;
+  int* rref;     /* per root block: 1 if refined */
+  int* rleaf;    /* per root block: its leaf, or its first child */
+  int nleaf;
+  int* lev;      /* per leaf: level 0 or 1 */
+  int* loc;      /* per leaf: 3 block coordinates at its level */
+  size_t vs, bs; /* doubles per variable and per leaf */
+} smr_mesh;
+
+static void smr_free(smr_mesh* m) {
+  free(m->rref); free(m->rleaf); free(m->lev); free(m->loc);
+}
+
+static int smr_init(smr_mesh* m, const or_params* p, const or_smr* s) {
+  memset(m, 0, sizeof *m);
+  m->p = *p;
+  const int g = or_nghost(p->recon);
+  int empty = 0;
+  for (int d = 0; d < 3; ++d) {
+    m->b[d] = s->block[d];
+    if (m->b[d] < 2 * g || (m->b[d] & 1) || p->n[d] % m->b[d]) return OR_ERR_ARG;
+    if ((p->bc[d][0] == OR_PERIODIC) != (p->bc[d][1] == OR_PERIODIC)) return OR_ERR_ARG;
+    m->nr[d] = p->n[d] / m->b[d];
+    if (s->lo[d] < 0 || s->hi[d] > m->nr[d]) return OR_ERR_ARG;
+    if (s->lo[d] >= s->hi[d]) empty = 1;
+  }
+  m->nroot = m->nr[0] * m->nr[1] * m->nr[2];
+  m->rref = calloc((size_t)m->nroot, sizeof(int));
+  m->rleaf = calloc((size_t)m->nroot, sizeof(int));
+  if (!m->rref || !m->rleaf) return OR_ERR_NOMEM;
+  int nleaf = 0;
+  for (int rz = 0; rz < m->nr[2]; ++rz)
+    for (int ry = 0; ry < m->nr[1]; ++ry)
+      for (int rx = 0; rx < m->nr[0]; ++rx) {
+        const int r = rx + m->nr[0] * (ry + m->nr[1] * rz);
+        const int in = !empty && rx >= s->lo[0] && rx < s->hi[0] && ry >= s->lo[1] &&
+                       ry < s->hi[1] && rz >= s->lo[2] && rz < s->hi[2];
+        m->rref[r] = in;
+        m->rleaf[r] = nleaf;
+        nleaf += in ? 8 : 1;
+      }
+  m->nleaf = nleaf;
+  m->lev = malloc((size_t)nleaf * sizeof(int));
+  m->loc = malloc((size_t)nleaf * 3 * sizeof(int));
+  if (!m->lev || !m->loc) return OR_ERR_NOMEM;
+  for (int rz = 0; rz < m->nr[2]; ++rz)
+    for (int ry = 0; ry < m->nr[1]; ++ry)
+      for (int rx = 0; rx < m->nr[0]; ++rx) {
+        const int r = rx + m->nr[0] * (ry + m->nr[1] * rz);
+        const int q0 = m->rleaf[r];
+        if (!m->rref[r]) {
+          m->lev[q0] = 0;
+          m->loc[3 * q0] = rx; m->loc[3 * q0 + 1] = ry; m->loc[3 * q0 + 2] = rz;
+          continue;
+        }
+        for (int c = 0; c < 8; ++c) {
+          const int q = q0 + c;
+          m->lev[q] = 1;
+          m->loc[3 * q] = 2 * rx + (c & 1);
+          m->loc[3 * q + 1] = 2 * ry + ((c >> 1) & 1);
+          m->loc[3 * q + 2] = 2 * rz + ((c >> 2) & 1);
+        }
+      }
+  m->vs = (size_t)m->b[0] * m->b[1] * m->b[2];
+  m->bs = 5 * m->vs;
+  return OR_OK;
+}
+
+static size_t smr_cell(const smr_mesh* m, int i, int j, int k) {
+  return ((size_t)k * m->b[1] + j) * m->b[0] + i;
+}
+
+/* Fine cell (i,j,k) (level-1 global indices, inside a refined root). */
+static double smr_fine(const smr_mesh* m, const double* U, int v, int i, int j, int k) {
+  const int lx = i / m->b[0], ly = j / m->b[1], lz = k / m->b[2];
+  const int r = lx / 2 + m->nr[0] * (ly / 2 + m->nr[1] * (lz / 2));
+  const int q = m->rleaf[r] + (lx & 1) + 2 * (ly & 1) + 4 * (lz & 1);
+  return U[(size_t)q * m->bs + (size_t)v * m->vs +
+           smr_cell(m, i - lx * m->b[0], j - ly * m->b[1], k - lz * m->b[2])];
+}
+
+/* Level-0 representation at coarse cell (I,J,K), inside the domain. */
+static double smr_rep0(const smr_mesh* m, const double* U, int v, int I, int J, int K) {
+  const int rx = I / m->b[0], ry = J / m->b[1], rz = K / m->b[2];
+  const int r = rx + m->nr[0] * (ry + m->nr[1] * rz);
+  if (!m->rref[r])
+    return U[(size_t)m->rleaf[r] * m->bs + (size_t)v * m->vs +
+             smr_cell(m, I - rx * m->b[0], J - ry * m->b[1], K - rz * m->b[2])];
+  double f[8];
+  for (int c = 0; c < 8; ++c)
+    f[c] = smr_fine(m, U, v, 2 * I + (c & 1), 2 * J + ((c >> 1) & 1), 2 * K + ((c >> 2) & 1));
+  return (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) * 0.125;
+}
+
+static double smr_minmod(double a, double b) {
+  if (!(a * b > 0.0)) return 0.0;
+  return fabs(a) < fabs(b) ? a : b;
+}
+
+/* Level-1 representation at fine cell (i,j,k), inside the domain. */
+static double smr_rep1(const smr_mesh* m, const double* U, int v, int i, int j, int k) {
+  const int r = i / (2 * m->b[0]) + m->nr[0] * (j / (2 * m->b[1]) + m->nr[1] * (k / (2 * m->b[2])));
+  if (m->rref[r]) return smr_fine(m, U, v, i, j, k);
+  const int c[3] = {i / 2, j / 2, k / 2};
+  const int f[3] = {i, j, k};
+  const double C = smr_rep0(m, U, v, c[0], c[1], c[2]);
+  double t[3];
+  for (int d = 0; d < 3; ++d) {
+    int lo[3] = {c[0], c[1], c[2]}, hi[3] = {c[0], c[1], c[2]};
+    lo[d] = src_index(c[d] - 1, m->p.n[d], m->p.bc[d][0], m->p.bc[d][1]);
+    hi[d] = src_index(c[d] + 1, m->p.n[d], m->p.bc[d][0], m->p.bc[d][1]);
+    const double dl = C - smr_rep0(m, U, v, lo[0], lo[1], lo[2]);
+    const double dr = smr_rep0(m, U, v, hi[0], hi[1], hi[2]) - C;
+    const double sd = smr_minmod(dl, dr);
+    t[d] = (f[d] & 1) ? sd : -sd;
+  }
+  return C + 0.25 * ((t[0] + t[1]) + t[2]);
+}
+
+/* Ghosted copy of leaf q: interior, then the face ghosts (ng deep, interior
+ * transverse extent) from the level representation; edges and corners, which
+ * the dimension-by-dimension stencil never reads, are set to 0. */
+static void smr_fill_leaf(const smr_mesh* m, const double* U, int q, const grid* G, double* Ug) {
+  const int L = m->lev[q], g = G->g;
+  const int base[3] = {m->loc[3 * q] * m->b[0], m->loc[3 * q + 1] * m->b[1], m->loc[3 * q + 2] * m->b[2]};
+  const int N[3] = {m->p.n[0] << L, m->p.n[1] << L, m->p.n[2] << L};
+  memset(Ug, 0, 5 * G->sv * sizeof(double));
+  for (int v = 0; v < 5; ++v)
+    for (int k = -g; k < m->b[2] + g; ++k)
+      for (int j = -g; j < m->b[1] + g; ++j)
+        for (int i = -g; i < m->b[0] + g; ++i) {
+          const int l[3] = {i, j, k};
+          int out = 0, dd = -1;
+          for (int d = 0; d < 3; ++d)
+            if (l[d] < 0 || l[d] >= m->b[d]) { ++out; dd = d; }
+          if (out == 0) {
+            Ug[at(G, v, i, j, k)] = U[(size_t)q * m->bs + (size_t)v * m->vs + smr_cell(m, i, j, k)];
+            continue;
+          }
+          if (out > 1) continue;
+          int gi[3] = {base[0] + i, base[1] + j, base[2] + k};
+          gi[dd] = src_index(gi[dd], N[dd], m->p.bc[dd][0], m->p.bc[dd][1]);
+          Ug[at(G, v, i, j, k)] = L == 0 ? smr_rep0(m, U, v, gi[0], gi[1], gi[2])
+                                         : smr_rep1(m, U, v, gi[0], gi[1], gi[2]);
+        }
+}
+
+static or_params smr_leaf_params(const smr_mesh* m, int q) {
+  or_params pl = m->p;
+  for (int d = 0; d < 3; ++d) {
+    pl.n[d] = m->b[d];
+    pl.dx[d] = m->lev[q] ? 0.5 * m->p.dx[d] : m->p.dx[d];
+  }
+  return pl;
+}
+
+/* Flux of face (i,j,k) along d of leaf q's flux array (face indices). */
+static double* smr_face(const smr_mesh* m, work* w, int d, int v, int i, int j, int k) {
+  const int fx = m->b[0] + (d == 0), fy = m->b[1] + (d == 1);
+  return &w->F[d][(size_t)v * w->fsv[d] + ((size_t)k * fy + j) * fx + i];
+}
+
+/* Replace the coarse fluxes on faces shared with refined roots by the mean
+ * of the 4 fine fluxes (the fine leaves' own, already in their work). */
+static void smr_correct_fluxes(const smr_mesh* m, work* w) {
+  for (int q = 0; q < m->nleaf; ++q) {
+    if (m->lev[q] != 0) continue;
+    const int rc[3] = {m->loc[3 * q], m->loc[3 * q + 1], m->loc[3 * q + 2]};
+    for (int d = 0; d < 3; ++d) {
+      const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+      for (int side = 0; side < 2; ++side) {
+        int rn[3] = {rc[0], rc[1], rc[2]};
+        rn[d] += side ? 1 : -1;
+        if (rn[d] < 0 || rn[d] >= m->nr[d]) {
+          if (m->p.bc[d][0] != OR_PERIODIC) continue;
+          rn[d] = (rn[d] + m->nr[d]) % m->nr[d];
+        }
+        if (!m->rref[rn[0] + m->nr[0] * (rn[1] + m->nr[1] * rn[2])]) continue;
+        /* fine cell just across the face, along d (level-1 global index) */
+        const int N1 = 2 * m->p.n[d];
+        const int fd = ((side ? 2 * (rc[d] + 1) * m->b[d] : 2 * rc[d] * m->b[d] - 1) + N1) % N1;
+        for (int b2 = 0; b2 < m->b[t2]; ++b2)
+          for (int b1 = 0; b1 < m->b[t1]; ++b1) {
+            int cf[3];
+            cf[d] = side ? m->b[d] : 0;
+            cf[t1] = b1;
+            cf[t2] = b2;
+            for (int v = 0; v < 5; ++v) {
+              double f[4];
+              for (int e = 0; e < 4; ++e) {
+                int gf[3];
+                gf[d] = fd;
+                gf[t1] = 2 * (rc[t1] * m->b[t1] + b1) + (e & 1);
+                gf[t2] = 2 * (rc[t2] * m->b[t2] + b2) + (e >> 1);
+                const int lx = gf[0] / m->b[0], ly = gf[1] / m->b[1], lz = gf[2] / m->b[2];
+                const int r = lx / 2 + m->nr[0] * (ly / 2 + m->nr[1] * (lz / 2));
+                const int qf = m->rleaf[r] + (lx & 1) + 2 * (ly & 1) + 4 * (lz & 1);
+                int lf[3] = {gf[0] - lx * m->b[0], gf[1] - ly * m->b[1], gf[2] - lz * m->b[2]};
+                lf[d] = side ? 0 : m->b[d];  /* the fine leaf's face on the coarse side */
+                f[e] = *smr_face(m, &w[qf], d, v, lf[0], lf[1], lf[2]);
+              }
+              *smr_face(m, &w[q], d, v, cf[0], cf[1], cf[2]) = ((f[0] + f[1]) + (f[2] + f[3])) * 0.25;
+            }
+          }
+      }
+    }
+  }
+}
+
+/* L for every leaf of the leaf-major state S: ghost fill, fluxes, flux
+ * correction, divergence (into w[q].L). */
+static long long smr_divergence(const smr_mesh* m, work* w, const double* S, int* bad) {
+  long long hits = 0;
+  int anybad = 0;
+  for (int q = 0; q < m->nleaf; ++q) {
+    const or_params pl = smr_leaf_params(m, q);
+    smr_fill_leaf(m, S, q, &w[q].G, w[q].U);
+    int b = 0;
+    hits += prims_and_fluxes(&pl, &w[q], &b);
+    anybad |= b;
+  }
+  smr_correct_fluxes(m, w);
+  for (int q = 0; q < m->nleaf; ++q) {
+    const or_params pl = smr_leaf_params(m, q);
+    flux_divergence(&pl, &w[q]);
+  }
+  if (bad) *bad = anybad;
+  return hits;
+}
+
+static void smr_stage(const smr_mesh* m, work* w, rk_coef k, const double* U0, const double* Ust,
+                      double h, double* Uout) {
+  for (int q = 0; q < m->nleaf; ++q) {
+    const or_params pl = smr_leaf_params(m, q);
+    const size_t o = (size_t)q * m->bs;
+    stage_formula(&pl, &w[q], k, U0 + o, Ust + o, h, Uout + o);
+  }
+}
+
+/* On any return, smr_close(m, *w) releases what was allocated. */
+static int smr_open(smr_mesh* m, work** w, const or_params* p, const or_smr* s) {
+  *w = NULL;
+  memset(m, 0, sizeof *m);
+  if (!p || !s) return OR_ERR_ARG;
+  if (p->recon < OR_PLM || p->recon > OR_PPMX || p->rk < 1 || p->rk > 4 || p->fofc) return OR_ERR_ARG;
+  int st = smr_init(m, p, s);
+  if (st != OR_OK) return st;
+  *w = calloc((size_t)m->nleaf, sizeof(work));
+  if (!*w) return OR_ERR_NOMEM;
+  for (int q = 0; q < m->nleaf; ++q) {
+    const or_params pl = smr_leaf_params(m, q);
+    if (work_alloc(&(*w)[q], &pl) != OR_OK) return OR_ERR_NOMEM;
+  }
+  return OR_OK;
+}
+
+static void smr_close(smr_mesh* m, work* w) {
+  if (w)
+    for (int q = 0; q < m->nleaf; ++q) work_free(&w[q]);  /* calloc'd: unset pointers are NULL */
+  free(w);
+  smr_free(m);
+}
+
+/* Number of leaves, and (when out != NULL) per leaf: level, x, y, z block
+ * coordinates at that level. Negative status on a bad configuration. */
+int or_smr_leaves(const or_params* p, const or_smr* s, int32_t* out) {
+  smr_mesh m;
+  int st = smr_init(&m, p, s);
+  if (st != OR_OK) { smr_free(&m); return -st; }
+  if (out)
+    for (int q = 0; q < m.nleaf; ++q) {
+      out[4 * q] = m.lev[q];
+      for (int d = 0; d < 3; ++d) out[4 * q + 1 + d] = m.loc[3 * q + d];
+    }
+  const int n = m.nleaf;
+  smr_free(&m);
+  return n;
+}
+
+/* CFL time step over all leaves, each at its own cell width. */
+double or_smr_new_dt(const or_params* p, const or_smr* s, const double* U) {
+  smr_mesh m;
+  if (smr_init(&m, p, s) != OR_OK) { smr_free(&m); return NAN; }
+  double dt = INFINITY;
+  for (int q = 0; q < m.nleaf; ++q) {
+    const or_params pl = smr_leaf_params(&m, q);
+    const double d = or_new_dt(&pl, U + (size_t)q * m.bs);
+    if (d < dt) dt = d;
+  }
+  smr_free(&m);
+  return dt;
+}
+
+/* Advance the leaf-major state by nsteps SSP-RK steps (the stage sequence of
+ * or_advance; every stage's L comes from smr_divergence). FOFC is not
+ * combined with refinement here. */
+int or_smr_advance(const or_params* p, const or_smr* s, double* U, int nsteps, double* t,
+                   double* dt, long long* floor_hits) {
+  if (!U || !t || !dt || nsteps < 0) return OR_ERR_ARG;
+  smr_mesh m;
+  work* w;
+  int st = smr_open(&m, &w, p, s);
+  if (st != OR_OK) { smr_close(&m, w); return st; }
+  const size_t nt = (size_t)m.nleaf * m.bs;
+  double* U1 = malloc(nt * sizeof(double));
+  double* U2 = malloc(nt * sizeof(double));
+  double* Q2 = p->rk == 4 ? malloc(nt * sizeof(double)) : NULL;
+  if (!U1 || !U2 || (p->rk == 4 && !Q2)) {
+    free(U1); free(U2); free(Q2); smr_close(&m, w);
+    return OR_ERR_NOMEM;
+  }
+  int status = OR_OK;
+  long long hits = 0;
+  for (int n = 0; n < nsteps; ++n) {
+    const double h = *dt;
+    const double* S = U;
+    const int nst = p->rk == 4 ? 10 : p->rk;
+    if (p->rk == 4) memcpy(Q2, U, nt * sizeof(double));
+    for (int stage = 1; stage <= nst; ++stage) {
+      int bad = 0;
+      hits += smr_divergence(&m, w, S, &bad);
+      if (bad) status = OR_ERR_STATE;
+      double* out = (stage & 1) ? U1 : U2;
+      if (p->rk == 4) {
+        const rk_coef k16 = {0.0, 1.0, 1.0 / 6.0}, kend = {1.0, 3.0 / 5.0, 1.0 / 10.0};
+        smr_stage(&m, w, stage < 10 ? k16 : kend, Q2, S, h, out);
+        if (stage == 5)
+          for (size_t c = 0; c < nt; ++c) {
+            Q2[c] = Q2[c] / 25.0 + 9.0 / 25.0 * out[c];
+            out[c] = 15.0 * Q2[c] - 5.0 * out[c];
+          }
+      } else {
+        smr_stage(&m, w, rk_stage(p->rk, stage), U, S, h, out);
+      }
+      S = out;
+    }
+    memcpy(U, S, nt * sizeof(double));
+    *t += h;
+    *dt = or_smr_new_dt(p, s, U);
+  }
+  if (floor_hits) *floor_hits += hits;
+  free(U1); free(U2); free(Q2);
+  smr_close(&m, w);
+  return status;
+}
+
+/* Tests: ghosted leaves [leaf][5][bz+2g][by+2g][bx+2g] (face ghosts from the
+ * level representation, edges and corners 0) and L per leaf after the flux
+ * correction ([leaf][5][bz][by][bx]). */
+int or_smr_fill_ghosts(const or_params* p, const or_smr* s, const double* U, double* Gout) {
+  smr_mesh m;
+  work* w;
+  int st = smr_open(&m, &w, p, s);
+  if (st != OR_OK) { smr_close(&m, w); return st; }
+  const size_t gs = 5 * w[0].G.sv;
+  for (int q = 0; q < m.nleaf; ++q) smr_fill_leaf(&m, U, q, &w[q].G, Gout + (size_t)q * gs);
+  smr_close(&m, w);
+  return OR_OK;
+}
+
+int or_smr_divergence(const or_params* p, const or_smr* s, const double* U, double* Lout,
+                      long long* floor_hits) {
+  smr_mesh m;
+  work* w;
+  int st = smr_open(&m, &w, p, s);
+  if (st != OR_OK) { smr_close(&m, w); return st; }
+  int bad = 0;
+  const long long h = smr_divergence(&m, w, U, &bad);
+  for (int q = 0; q < m.nleaf; ++q) memcpy(Lout + (size_t)q * m.bs, w[q].L, m.bs * sizeof(double));
+  if (floor_hits) *floor_hits = h;
+  smr_close(&m, w);
+  return bad ? OR_ERR_STATE : OR_OK;
 }

@@ -56,15 +56,20 @@ class Problem:
     p_floor: float = 1e-13
     fofc: int = 0                 # first-order flux correction (Sec. 3) on/off
     rk: int = 2                   # SSP-RK order (Sec. 3): 1, 2, 3 or 4 (SSPRK(10,4))
+    refine: tuple | None = None   # ((lo), (hi)) root blocks refined once; U is then
+                                  # leaf-major [leaf][5][bz][by][bx] (see to_leaves)
     name: str = ""
     meta: dict = field(default_factory=dict)
 
     @property
     def dx(self):
+        """Cell widths of the root (level-0) grid."""
         return tuple((self.hi[d] - self.lo[d]) / self.n[d] for d in range(3))
 
     @property
     def cells(self):
+        if self.refine is not None:
+            return int(self.U.shape[0]) * int(np.prod(self.block))
         return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
 
     def with_(self, **kw):
@@ -527,3 +532,41 @@ def generate_state(pb) -> np.ndarray:
         full = sedov(N=N, seed=sub)
     assert full.n == tuple(pb.n) and full.bc == pb.bc and full.lo == pb.lo
     return full.U
+
+
+# --------------------------------------------------------------------------
+# Statically refined meshes (state layout only; no solver arithmetic)
+# --------------------------------------------------------------------------
+def to_leaves(U0, U1, leaves, block):
+    """Leaf-major state [leaf][5][bz][by][bx] of a refined mesh: leaf
+    (level, lx, ly, lz) takes block (lx, ly, lz) of the global state at its
+    level, U0 [5][nz][ny][nx] for level 0 and U1 (twice the cells per axis)
+    for level 1. ``leaves`` comes from the solver's leaf query."""
+    bx, by, bz = (int(b) for b in block)
+    lv = np.asarray(leaves).reshape(-1, 4)
+    out = np.empty((len(lv), 5, bz, by, bx), dtype=np.float64)
+    for q, (L, lx, ly, lz) in enumerate(lv):
+        src = U0 if L == 0 else U1
+        out[q] = src[:, lz * bz:(lz + 1) * bz, ly * by:(ly + 1) * by, lx * bx:(lx + 1) * bx]
+    return out
+
+
+def from_leaves(UL, leaves, block, level):
+    """Inverse of ``to_leaves`` for one level: a dict {(lx, ly, lz): block}
+    of that level's leaves."""
+    lv = np.asarray(leaves).reshape(-1, 4)
+    return {(int(r[1]), int(r[2]), int(r[3])): UL[q] for q, r in enumerate(lv) if r[0] == level}
+
+
+def refined(make, refine, leaves):
+    """A problem on a statically refined mesh. ``make(s)`` builds the uniform
+    problem at s times the root resolution (s = 1, 2) on the same domain with
+    the same block size; ``refine`` = ((lo), (hi)) in root blocks; ``leaves``
+    fixes the leaf order. Each leaf's cells are sampled from the problem at
+    its own resolution."""
+    p1 = make(1)
+    lv = np.asarray(leaves).reshape(-1, 4)
+    p2 = make(2) if (lv[:, 0] == 1).any() else None
+    UL = to_leaves(p1.U, None if p2 is None else p2.U, lv, p1.block)
+    return p1.with_(U=UL, refine=(tuple(refine[0]), tuple(refine[1])),
+                    name=(p1.name + " refined").strip())

@@ -15,6 +15,7 @@ import oracle
 import test_oracle_f2 as f2
 import test_oracle_fofc as fofc
 import test_oracle_physics as phys
+import test_oracle_smr as smr
 import test_oracle_units as units
 from paper_2409_16053_amd import problems as P
 
@@ -64,6 +65,16 @@ MUTANTS = [
     ("llf_dissipation_sign", "0.5 * (fl[q] + fr[q]) - 0.5 * a * (ur[q] - ul[q])",
      "0.5 * (fl[q] + fr[q]) + 0.5 * a * (ur[q] - ul[q])"),
     ("fofc_wrong_cell_side", "const int li = i - di * (1 - side)", "const int li = i - di * side"),
+    ("smr_restriction_weight", "((f[4] + f[5]) + (f[6] + f[7]))) * 0.125;", "((f[4] + f[5]) + (f[6] + f[7]))) * 0.12;"),
+    ("smr_prolongation_child_sign", "t[d] = (f[d] & 1) ? sd : -sd;", "t[d] = (f[d] & 1) ? -sd : sd;"),
+    ("smr_prolongation_offset", "return C + 0.25 * ((t[0] + t[1]) + t[2]);", "return C + 0.5 * ((t[0] + t[1]) + t[2]);"),
+    ("smr_prolongation_unlimited_slope", "return fabs(a) < fabs(b) ? a : b;", "return 0.5 * (a + b) + 0.0 * fabs(a);"),
+    ("smr_child_order", "const int q = m->rleaf[r] + (lx & 1) + 2 * (ly & 1) + 4 * (lz & 1);",
+     "const int q = m->rleaf[r] + (lx & 1) + 2 * (lz & 1) + 4 * (ly & 1);"),
+    ("smr_flux_correction_dropped", "*smr_face(m, &w[q], d, v, cf[0], cf[1], cf[2]) = ((f[0] + f[1]) + (f[2] + f[3])) * 0.25;",
+     "(void)f;"),
+    ("smr_fine_face_side", "lf[d] = side ? 0 : m->b[d];", "lf[d] = side ? m->b[d] : 0;"),
+    ("smr_fine_cell_width", "pl.dx[d] = m->lev[q] ? 0.5 * m->p.dx[d] : m->p.dx[d];", "pl.dx[d] = m->p.dx[d];"),
 ]
 
 
@@ -110,6 +121,11 @@ def _fast_pins(O):
     yield lambda: f2.test_ppmx_parabola_monotone_on_monotone_data(O)
     yield lambda: f2.test_time_order_of_the_integrators(O, P.WENOZ, 3, 256, (0.8, 0.4), 2.75, 3.3)
     yield lambda: f2.test_time_order_by_richardson(O, 4, 4.0)
+    yield lambda: smr.test_face_ghosts_exact_for_linear_fields(O, P.PLM)
+    yield lambda: smr.test_face_ghosts_match_independent_restriction_and_prolongation(O)
+    yield lambda: smr.test_uniform_state_stays_uniform_bitwise(O, P.PERIODIC, P.PLM)
+    yield lambda: smr.test_periodic_refined_mesh_conserves(O, P.PLM, 2)
+    yield lambda: smr.test_full_refinement_equals_uniform_fine_grid_bitwise(O, P.PERIODIC)
 
 
 def test_unplanted_build_passes_fast_pins(tmp_path):

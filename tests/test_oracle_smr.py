@@ -1,0 +1,328 @@
+"""Pins of the CPU reference solver on statically refined meshes (Sec. 2:
+MeshBlocks on two levels, ghost zones across a level change filled by
+restriction and prolongation, fluxes on coarse faces next to fine blocks
+replaced by the fine fluxes).
+
+* The leaves tile the domain exactly once.
+* Face ghosts are exact for linear fields: restriction of a linear field is
+  its coarse cell-centre value, and limited linear prolongation reproduces a
+  linear field exactly. An independent numpy evaluation of both operators
+  (reshape means, rolled minmod slopes) on random data agrees.
+* With nothing refined the solver equals the uniform solver bitwise; with
+  every root refined it equals the uniform solver at twice the resolution
+  bitwise (refinement that changes nothing changes no bit).
+* Totals of mass, momentum and energy stay constant to roundoff on a
+  periodic mesh with a refined box; a uniform state stays uniform bitwise;
+  permuting the axes of the whole configuration permutes the result (up to
+  the rounding of sums taken in a fixed axis order).
+* A smooth wave crossing the refinement boundary keeps second-order
+  convergence and stays no worse than the coarse uniform mesh; a Sod shock
+  crossing it keeps its star states.
+"""
+import numpy as np
+import pytest
+
+import exact
+from paper_2409_16053_amd import problems as P
+
+
+def _refined(O, make, refine):
+    base = make(1).with_(refine=refine)
+    return P.refined(make, refine, O.smr_leaves(base))
+
+
+def _totals(pb, U, lv):
+    vol = np.prod(pb.dx) * np.where(lv[:, 0] == 0, 1.0, 0.125)
+    s = np.einsum("q,qv->v", vol, U.reshape(U.shape[0], 5, -1).sum(-1))
+    a = np.einsum("q,qv->v", vol, np.abs(U).reshape(U.shape[0], 5, -1).sum(-1))
+    return s, a
+
+
+# ------------------------------------------------------------------ leaves
+def test_leaves_tile_the_domain_once(oracle_lib):
+    pb = P.uniform(n=(32, 24, 16), rho=1.0, v=(0, 0, 0), p=1.0, bc=P.PERIODIC)
+    pb = pb.with_(block=(8, 8, 8), refine=((1, 0, 1), (3, 2, 2)))
+    lv = oracle_lib.smr_leaves(pb)
+    nroot = 4 * 3 * 2
+    nref = 2 * 2 * 1
+    assert len(lv) == nroot - nref + 8 * nref
+    cover = np.zeros((32, 48, 64), dtype=np.int32)  # level-1 cells, [z][y][x]
+    for L, lx, ly, lz in lv:
+        s = 8 * (2 - L)  # footprint of the leaf in level-1 cells
+        cover[lz * s:(lz + 1) * s, ly * s:(ly + 1) * s, lx * s:(lx + 1) * s] += 1
+        if L == 1:
+            r = (lx // 2, ly // 2, lz // 2)
+            assert all(pb.refine[0][d] <= r[d] < pb.refine[1][d] for d in range(3))
+    assert np.all(cover == 1)
+
+
+@pytest.mark.parametrize("bad", [dict(n=(30, 16, 16), block=(5, 8, 8)), dict(block=(2, 8, 8)),
+                                 dict(refine=((0, 0, 0), (5, 1, 1))), dict(fofc=1)])
+def test_bad_refined_mesh_is_rejected(oracle_lib, bad):
+    pb = P.uniform(n=(24, 16, 16), rho=1.0, v=(0, 0, 0), p=1.0, bc=P.PERIODIC)
+    pb = pb.with_(block=(8, 8, 8), refine=((0, 0, 0), (1, 1, 1)))
+    pb = pb.with_(**bad)
+    if "fofc" in bad:
+        U = np.ones((len(oracle_lib.smr_leaves(pb)), 5, 8, 8, 8))
+        U[:, 4] = 2.0
+        assert oracle_lib.advance(pb, 1, U=U, dt=1e-3)["status"] == oracle_lib.ERR_ARG
+    else:
+        with pytest.raises(ValueError):
+            oracle_lib.smr_leaves(pb)
+
+
+# ------------------------------------------------------------------ ghosts
+def _linear_state(pb, lv, coef, level_shift):
+    """Cell-centre values a_v + b_v x + c_v y + d_v z at each leaf's level."""
+    bx, by, bz = pb.block
+    out = np.empty((len(lv), 5, bz, by, bx))
+    for q, (L, lx, ly, lz) in enumerate(lv):
+        dx = [pb.dx[d] / (2 ** L) for d in range(3)]
+        x = pb.lo[0] + (lx * bx + np.arange(bx) + 0.5) * dx[0]
+        y = pb.lo[1] + (ly * by + np.arange(by) + 0.5) * dx[1]
+        z = pb.lo[2] + (lz * bz + np.arange(bz) + 0.5) * dx[2]
+        for v in range(5):
+            a, b, c, d = coef[v]
+            out[q, v] = a + b * x[None, None, :] + c * y[None, :, None] + d * z[:, None, None]
+    return out
+
+
+@pytest.mark.parametrize("recon", [P.PLM, P.PPM4])
+def test_face_ghosts_exact_for_linear_fields(oracle_lib, recon):
+    g = P.NGHOST[recon]
+    pb = P.uniform(n=(32, 32, 32), rho=1.0, v=(0, 0, 0), p=1.0, bc=P.OUTFLOW)
+    pb = pb.with_(block=(8, 8, 8), recon=recon, refine=((1, 1, 1), (3, 3, 2)))
+    lv = oracle_lib.smr_leaves(pb)
+    rng = np.random.default_rng(5)
+    coef = rng.uniform(-1, 1, size=(5, 4)) + np.array([3.0, 0, 0, 0])
+    U = _linear_state(pb, lv, coef, 0)
+    G = oracle_lib.smr_fill_ghosts(pb.with_(U=U))
+    bx, by, bz = pb.block
+    checked = 0
+    for q, (L, lx, ly, lz) in enumerate(lv):
+        dx = [pb.dx[d] / (2 ** L) for d in range(3)]
+        N = [pb.n[d] * 2 ** L for d in range(3)]
+        base = (lx * bx, ly * by, lz * bz)
+        for d in range(3):
+            for side in (-1, 1):
+                for layer in range(g):
+                    loc = [slice(g, g + bx), slice(g, g + by), slice(g, g + bz)]
+                    idx = -1 - layer if side < 0 else pb.block[d] + layer
+                    gidx = base[d] + idx
+                    if gidx < 0 or gidx >= N[d]:
+                        continue  # outflow copy, not linear
+                    loc[d] = g + idx
+                    got = G[q][:, loc[2], loc[1], loc[0]]
+                    cen = [pb.lo[e] + (base[e] + np.arange(pb.block[e]) + 0.5) * dx[e] for e in range(3)]
+                    cen[d] = np.array([pb.lo[d] + (gidx + 0.5) * dx[d]])
+                    want = np.stack([coef[v, 0] + coef[v, 1] * cen[0][None, None, :]
+                                     + coef[v, 2] * cen[1][None, :, None]
+                                     + coef[v, 3] * cen[2][:, None, None] for v in range(5)])
+                    assert np.allclose(got, want.reshape(got.shape), rtol=0, atol=1e-13), (q, d, side, layer)
+                    checked += 1
+    assert checked > 100
+
+
+def _rep_numpy(pb, lv, U):
+    """Level-0 and level-1 representations of a periodic refined state, by a
+    route of their own: block assembly, reshape means, rolled minmod slopes."""
+    bx, by, bz = pb.block
+    nx, ny, nz = pb.n
+    fine = np.full((5, 2 * nz, 2 * ny, 2 * nx), np.nan)
+    coarse = np.full((5, nz, ny, nx), np.nan)
+    for q, (L, lx, ly, lz) in enumerate(lv):
+        tgt = fine if L else coarse
+        tgt[:, lz * bz:(lz + 1) * bz, ly * by:(ly + 1) * by, lx * bx:(lx + 1) * bx] = U[q]
+    means = fine.reshape(5, nz, 2, ny, 2, nx, 2).mean(axis=(2, 4, 6))
+    R0 = np.where(np.isnan(coarse), means, coarse)
+    slopes = []
+    for ax in (3, 2, 1):  # x, y, z array axes
+        dl = R0 - np.roll(R0, 1, axis=ax)
+        dr = np.roll(R0, -1, axis=ax) - R0
+        s = np.where(dl * dr > 0, np.where(np.abs(dl) < np.abs(dr), dl, dr), 0.0)
+        slopes.append(s)
+    up = lambda a: a.repeat(2, axis=1).repeat(2, axis=2).repeat(2, axis=3)
+    sg = [np.where(np.arange(2 * n) % 2 == 1, 1.0, -1.0) for n in (nx, ny, nz)]
+    prol = up(R0) + 0.25 * ((up(slopes[0]) * sg[0][None, None, None, :]
+                             + up(slopes[1]) * sg[1][None, None, :, None])
+                            + up(slopes[2]) * sg[2][None, :, None, None])
+    R1 = np.where(np.isnan(fine), prol, fine)
+    return R0, R1
+
+
+def test_face_ghosts_match_independent_restriction_and_prolongation(oracle_lib):
+    pb = P.uniform(n=(32, 16, 24), rho=1.0, v=(0, 0, 0), p=1.0, bc=P.PERIODIC)
+    pb = pb.with_(block=(8, 8, 8), recon=P.PPM4, refine=((0, 0, 1), (2, 1, 2)))
+    lv = oracle_lib.smr_leaves(pb)
+    rng = np.random.default_rng(11)
+    U = rng.uniform(0.5, 2.0, size=(len(lv), 5, 8, 8, 8))
+    G = oracle_lib.smr_fill_ghosts(pb.with_(U=U))
+    R0, R1 = _rep_numpy(pb, lv, U)
+    g = 3
+    for q, (L, lx, ly, lz) in enumerate(lv):
+        R = R1 if L else R0
+        N = R.shape[1:][::-1]
+        base = (lx * 8, ly * 8, lz * 8)
+        ii = [np.arange(base[e] - g, base[e] + 8 + g) % N[e] for e in range(3)]
+        full = R[:, ii[2]][:, :, ii[1]][:, :, :, ii[0]]
+        mask = np.zeros((8 + 2 * g,) * 3, dtype=bool)  # face ghosts only
+        inner = slice(g, g + 8)
+        for d in range(3):
+            m = [inner, inner, inner]
+            m[2 - d] = np.r_[0:g, 8 + g:8 + 2 * g]
+            mask[np.ix_(*[np.arange(8 + 2 * g)[s] for s in m])] = True
+        np.testing.assert_allclose(G[q][:, mask], full[:, mask], rtol=2e-15, atol=0)
+
+
+# --------------------------------------------------- refinement that changes nothing
+def _global_to_leaves(O, pb):
+    lv = O.smr_leaves(pb)
+    return P.to_leaves(pb.U, None, lv, pb.block), lv
+
+
+@pytest.mark.parametrize("recon,rk", [(P.PLM, 2), (P.WENOZ, 3)])
+def test_empty_refinement_equals_uniform_bitwise(oracle_lib, recon, rk):
+    pb = P.turbulence(N=32, seed=7, kmax=6).with_(block=(16, 8, 16), recon=recon, rk=rk)
+    ref = oracle_lib.advance(pb, 4)
+    pr = pb.with_(refine=((0, 0, 0), (0, 0, 0)))
+    UL, lv = _global_to_leaves(oracle_lib, pr)
+    r = oracle_lib.advance(pr.with_(U=UL), 4)
+    assert np.array_equal(r["U"], P.to_leaves(ref["U"], None, lv, pb.block))
+    assert r["dt"] == ref["dt"] and r["t"] == ref["t"]
+
+
+@pytest.mark.parametrize("bc", [P.PERIODIC, P.OUTFLOW])
+def test_full_refinement_equals_uniform_fine_grid_bitwise(oracle_lib, bc):
+    make = lambda s: P.sedov(N=16 * s, seed=3).with_(block=(8, 8, 8), bc=((bc, bc),) * 3)
+    fine = make(2)
+    ref = oracle_lib.advance(fine, 5)
+    pr = _refined(oracle_lib, make, ((0, 0, 0), (2, 2, 2)))
+    lv = oracle_lib.smr_leaves(pr)
+    assert (lv[:, 0] == 1).all()
+    r = oracle_lib.advance(pr, 5)
+    assert np.array_equal(r["U"], P.to_leaves(None, ref["U"], lv, (8, 8, 8)))
+    assert r["dt"] == ref["dt"]
+
+
+# ------------------------------------------------------------ conservation
+@pytest.mark.parametrize("recon,rk", [(P.PLM, 2), (P.WENOZ, 3), (P.PPM4, 4)])
+def test_periodic_refined_mesh_conserves(oracle_lib, recon, rk):
+    make = lambda s: P.turbulence(N=16 * s, seed=9, kmax=4).with_(block=(8, 8, 8), recon=recon, rk=rk)
+    pr = _refined(oracle_lib, make, ((1, 0, 0), (2, 2, 1)))
+    lv = oracle_lib.smr_leaves(pr)
+    r = oracle_lib.advance(pr, 4)
+    assert r["status"] == 0
+    s0, a0 = _totals(pr, pr.U, lv)
+    s1, a1 = _totals(pr, r["U"], lv)
+    nst = {2: 2, 3: 3, 4: 10}[rk]
+    bound = 8 * np.finfo(float).eps * np.sqrt(pr.cells * nst * 4)
+    assert np.all(np.abs(s1 - s0) <= bound * (a0 + a1)), (s1 - s0) / (a0 + a1)
+    # L itself: the volume-weighted sum of the divergence is zero on a periodic mesh
+    L, st, _ = oracle_lib.smr_divergence(pr)
+    sl, al = _totals(pr, L, lv)
+    assert np.all(np.abs(sl) <= 64 * np.finfo(float).eps * al)
+
+
+@pytest.mark.parametrize("bc", [P.PERIODIC, P.OUTFLOW])
+@pytest.mark.parametrize("recon", [P.PLM, P.PPMX])
+def test_uniform_state_stays_uniform_bitwise(oracle_lib, bc, recon):
+    make = lambda s: P.uniform(n=(16 * s, 16 * s, 8 * s), rho=1.3, v=(0.3, -0.2, 0.1), p=0.7,
+                               bc=bc).with_(block=(8, 8, 8), recon=recon)
+    pr = _refined(oracle_lib, make, ((0, 1, 0), (1, 2, 1)))
+    r = oracle_lib.advance(pr, 3)
+    assert np.array_equal(r["U"], pr.U)
+
+
+def test_axis_permutation_bitwise(oracle_lib):
+    # (x, y, z) -> (y, z, x): the mesh, the refined box and the state rotate together
+    make = lambda s: P.sedov(N=16 * s, seed=5, noise=1e-6).with_(block=(8, 8, 8))
+    box = ((0, 1, 0), (1, 2, 2))
+    pa = _refined(oracle_lib, make, box)
+    ra = oracle_lib.advance(pa, 4)
+    la = oracle_lib.smr_leaves(pa)
+    # rotated problem: new x = old y, new y = old z, new z = old x
+    rot_box = ((box[0][1], box[0][2], box[0][0]), (box[1][1], box[1][2], box[1][0]))
+    def rot_state(U):  # [leaf][5][z][y][x]: B[z', y', x'] = A[y', x', z'], momenta permuted
+        out = np.empty_like(U)
+        for v, w in ((0, 0), (1, 2), (2, 3), (3, 1), (4, 4)):
+            out[:, v] = np.transpose(U[:, w], axes=(0, 3, 1, 2))
+        return out
+    pb = pa.with_(refine=rot_box)
+    lb = oracle_lib.smr_leaves(pb)
+    pos_a = {(int(r[0]), int(r[1]), int(r[2]), int(r[3])): q for q, r in enumerate(la)}
+    order = [pos_a[(int(L), int(lz), int(lx), int(ly))] for L, lx, ly, lz in lb]
+    pb = pb.with_(U=rot_state(pa.U[order]))
+    rb = oracle_lib.advance(pb, 4)
+    # equal up to rounding: sums over x, y, z (divergence, restriction,
+    # prolongation offsets) run in a fixed axis order, which the rotation changes
+    want = rot_state(ra["U"][order])
+    err = np.abs(rb["U"] - want).reshape(len(lb), 5, -1).max(axis=(0, 2))
+    scale = np.abs(want).reshape(len(lb), 5, -1).max(axis=(0, 2))
+    assert np.all(err <= 1e-13 * scale), err / scale
+    assert abs(rb["dt"] / ra["dt"] - 1) < 1e-14
+
+
+# -------------------------------------------------------- accuracy through the boundary
+def _entropy_error(O, N, refine):
+    make = lambda s: P.entropy_wave(N=N * s, amp=0.2, axis=0, ntrans=8 * s).with_(
+        block=(N // 4, 8, 8), cfl=0.2)
+    pr = _refined(O, make, refine) if refine else make(1)
+    U, t = pr.U, 0.0
+    dt = O.new_dt(pr, U)
+    while t < 1.0 - 1e-12:
+        dt = min(dt, 1.0 - t)
+        r = O.advance(pr, 1, U=U, t=t, dt=dt)
+        U, t, dt = r["U"], r["t"], r["dt"]
+    if refine:
+        ex = P.refined(lambda s: P.entropy_wave(N=N * s, amp=0.2, axis=0, ntrans=8 * s, t=t)
+                       .with_(block=(N // 4, 8, 8)), refine, O.smr_leaves(pr))
+        lv = O.smr_leaves(pr)
+        w = np.where(lv[:, 0] == 0, 1.0, 0.125)
+        return float((w[:, None, None, None] * np.abs(U[:, 0] - ex.U[:, 0])).sum()
+                     / w.sum() / U[0, 0].size / 0.2)
+    ex = P.entropy_wave(N=N, amp=0.2, axis=0, ntrans=8, t=t).U
+    return float(np.abs(U[0] - ex[0]).mean() / 0.2)
+
+
+def test_entropy_wave_through_refinement_second_order(oracle_lib):
+    # the wave crosses a refined block twice per period (x blocks 1 of 4)
+    box = ((1, 0, 0), (2, 1, 1))
+    # (N = 16 is pre-asymptotic for PLM: the uniform mesh converges at 1.3 there)
+    e32, e64 = _entropy_error(oracle_lib, 32, box), _entropy_error(oracle_lib, 64, box)
+    u32 = _entropy_error(oracle_lib, 32, None)
+    assert np.log2(e32 / e64) >= 1.8, (e32, e64)
+    assert e32 <= u32, (e32, u32)
+
+
+def test_sod_shock_crosses_refinement(oracle_lib):
+    # tube along x on [0, 1], discontinuity at 0.5, refined blocks at
+    # x in [0.625, 0.875): the shock enters, crosses and leaves the fine
+    # region; the post-shock plateau keeps the exact density
+    gamma = 1.4
+    make = lambda s: P.sod(N=64 * s, axis=0, ntrans=8 * s, gamma=gamma).with_(block=(8, 8, 8))
+    pr = _refined(oracle_lib, make, ((5, 0, 0), (7, 1, 1)))
+    lv = oracle_lib.smr_leaves(pr)
+    U, t = pr.U, 0.0
+    dt = oracle_lib.new_dt(pr, U)
+    while t < 0.25:
+        r = oracle_lib.advance(pr, 1, U=U, t=t, dt=dt)
+        U, t, dt = r["U"], r["t"], r["dt"]
+    WL, WR = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    ps, us = exact.star_state(WL, WR, gamma)
+    rho_sr = exact.star_densities(WL, WR, gamma)[1]
+    a_r = np.sqrt(gamma * WR[2] / WR[0])
+    s_r = WR[1] + a_r * np.sqrt((gamma + 1) / (2 * gamma) * ps / WR[2] + (gamma - 1) / (2 * gamma))
+    # coarse leaves at x in [0.5, 0.625): between contact and shock at t = 0.25
+    xs, rho = [], []
+    for q, (L, lx, ly, lz) in enumerate(lv):
+        dx = 1.0 / (64 * 2 ** L)
+        x = (lx * 8 + np.arange(8) + 0.5) * dx
+        xs.append(x)
+        rho.append(U[q, 0, 0, 0])
+    xs, rho = np.concatenate(xs), np.concatenate(rho)
+    xc = 0.5 + us * t
+    xsh = 0.5 + s_r * t
+    sel = (xs > xc + 0.03) & (xs < xsh - 0.03)
+    assert sel.sum() >= 3
+    assert np.all(np.abs(rho[sel] / rho_sr - 1) < 0.02), rho[sel]
+    assert xsh > 0.875  # the shock has left the fine region again
