@@ -84,7 +84,21 @@ enum { HY_FP64 = 0, HY_MIXED = 1 };
  *              (the ten-stage SSPRK(10,4) of Ketcheson); 0 selects 2. RK3
  *              and RK4 add a third state register to the workspace.
  *  rho_floor, p_floor  floors applied to the primitive state only (U is
- *              never modified by a floor); each firing is counted.          */
+ *              never modified by a floor); each firing is counted.
+ *  refine_lo[3], refine_hi[3]  static mesh refinement (Sec. 2: MeshBlocks
+ *              of equal cell count on a tree of levels): the root blocks
+ *              (the n / block grid) with refine_lo <= index < refine_hi on
+ *              every axis are refined once, each into 8 blocks of block[]
+ *              cells at half the cell width. An empty box (refine_lo >=
+ *              refine_hi on any axis) means no refinement. With refinement,
+ *              block[] must be even and >= twice the ghost depth, and fofc
+ *              must be 0. Ghost cells across a level change hold the coarse
+ *              mean of the 8 fine cells (restriction) or, on the fine side,
+ *              the coarse value plus a quarter of the minmod-limited coarse
+ *              slope per axis towards the fine cell (prolongation); the flux
+ *              through a coarse face next to 4 fine faces is their mean, so
+ *              the update is conservative. The state is then exchanged per
+ *              leaf block (hy_leaves, hy_set_state).                        */
 typedef struct {
   int32_t n[3];
   int32_t block[3];
@@ -97,13 +111,25 @@ typedef struct {
   int32_t fofc;
   int32_t rk;
   double rho_floor, p_floor;
+  int32_t refine_lo[3], refine_hi[3];
 } hy_config;
+
+/* Leaf blocks of a configuration's mesh, in the order of the leaf-major
+ * state: root blocks with x fastest, then y, then z; a refined root block
+ * stands for its 8 children, child x offset fastest, then y, then z. Returns
+ * the number of leaves (the root block count without refinement), and, when
+ * out != NULL, writes per leaf 4 int32: level (0 or 1) and the block's x, y, z
+ * coordinates in blocks of its level. Returns -1 for an invalid configuration
+ * (message in hy_last_error). */
+int32_t hy_leaves(const hy_config* cfg, int32_t* out);
 
 /* Device bytes one problem needs (the MeshBlockPack of Sec. 2, "Data
  * locality", with no stored ghost cells): two FP64 state registers of
  * 5 x cells doubles each (the step-start state and the RK stage state; three
  * with rk = 3 or 4), a 1024-byte header, and with fofc one byte of flag per
- * cell.
+ * cell. With refinement each register also holds one extra block per leaf
+ * face that meets a different level (its ghost slab), and the workspace holds
+ * the leaf, root and face tables.
  * Returns 0 for an invalid configuration (message in hy_last_error). */
 size_t hy_workspace_bytes(const hy_config* cfg);
 
@@ -130,7 +156,9 @@ enum {
  * double[5][nz][ny][nx], x fastest, variables rho, Mx, My, Mz, E, located as
  * `where` says. The library scatters it into its MeshBlocks (host data is
  * staged through the problem's second state register) and computes the first
- * time step from it (Eq. 3). Clears the bad-state flag. Resets neither t nor
+ * time step from it (Eq. 3). On a refined mesh U is instead the leaf-major
+ * state double[leaf][5][bz][by][bx] in hy_leaves order, each leaf at its own
+ * resolution, copied as is. Clears the bad-state flag. Resets neither t nor
  * the step count. */
 hy_status hy_set_state(hy_problem* p, const double* U, int where, void* hip_stream);
 

@@ -1,12 +1,14 @@
 // hy_api.hip -- host runtime behind the C ABI of include/hy.h.
 //
 // Owns host metadata only: the problem's workspace (two FP64 MeshBlockPack
-// registers, three for RK3, and a 512-byte header) is provided by the caller. Launch planning
+// registers, three for RK3 and RK4, a 1024-byte header, and the tables of a
+// refined mesh) is provided by the caller. Launch planning
 // turns a set of problems into per-stage launch arguments: every problem's
 // MeshBlocks are cut into x-y tiles and z-chunks, and one launch per RK
 // stage covers the tiles of all problems that share a compiled kernel
 // (the paper's MeshBlockPack, Sec. 2, generalised to many problems).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -65,6 +67,13 @@ int stages_of(const hy_config* c) {
 }
 int registers_of(const hy_config* c) { return c->rk >= 3 ? 3 : 2; }
 
+// Static refinement: a non-empty box of refined root blocks.
+bool has_refine(const hy_config* c) {
+  for (int d = 0; d < 3; ++d)
+    if (c->refine_lo[d] >= c->refine_hi[d]) return false;
+  return true;
+}
+
 bool validate(const hy_config* c, std::string& msg) {
   if (!c) { msg = "config is NULL"; return false; }
   if (c->recon != HY_PLM && c->recon != HY_PPM4 && c->recon != HY_WENOZ && c->recon != HY_PPMX) {
@@ -94,15 +103,116 @@ bool validate(const hy_config* c, std::string& msg) {
     msg = "floors must be finite and >= 0";
     return false;
   }
-  const double cells = (double)c->n[0] * c->n[1] * c->n[2];
+  if (has_refine(c)) {
+    if (c->fofc) { msg = "fofc cannot be combined with mesh refinement"; return false; }
+    for (int d = 0; d < 3; ++d) {
+      if ((c->block[d] & 1) || c->block[d] < 2 * ng) {
+        msg = "with refinement, block must be even and >= twice the ghost depth";
+        return false;
+      }
+      if (c->refine_lo[d] < 0 || c->refine_hi[d] > c->n[d] / c->block[d]) {
+        msg = "refined box outside the root block grid";
+        return false;
+      }
+    }
+  }
+  const double cells = (double)c->n[0] * c->n[1] * c->n[2] * (has_refine(c) ? 8.0 : 1.0);
   if (cells * 5.0 * 8.0 * registers_of(c) > 4.0e12) { msg = "mesh too large"; return false; }
   const double blk = (double)c->block[0] * c->block[1] * c->block[2] * 5.0;
   if (blk > 2.0e9) { msg = "MeshBlock too large"; return false; }
   return true;
 }
 
+// The leaf, slab, root and coarse-face tables of a refined mesh (Sec. 2:
+// MeshBlocks on two levels). Leaves: root blocks x fastest; a refined root
+// stands for its 8 children, child x offset fastest. A leaf face whose
+// neighbour region is at the other level gets a slab: one extra block in each
+// register that holds the ghost cells there, at the leaf's level.
+struct SmrLayout {
+  int nr[3] = {0, 0, 0};
+  int nleaf = 0, nvirt = 0, ncf = 0;
+  std::vector<int32_t> binfo, vinfo, rinfo, cfinfo;
+};
+
+void build_smr(const hy_config* c, SmrLayout& L) {
+  for (int d = 0; d < 3; ++d) L.nr[d] = c->n[d] / c->block[d];
+  const int nroot = L.nr[0] * L.nr[1] * L.nr[2];
+  L.rinfo.assign(2 * (size_t)nroot, 0);
+  std::vector<std::array<int, 4>> leaf;  // level, x, y, z
+  for (int rz = 0; rz < L.nr[2]; ++rz)
+    for (int ry = 0; ry < L.nr[1]; ++ry)
+      for (int rx = 0; rx < L.nr[0]; ++rx) {
+        const int r = rx + L.nr[0] * (ry + L.nr[1] * rz);
+        const bool ref = rx >= c->refine_lo[0] && rx < c->refine_hi[0] && ry >= c->refine_lo[1] &&
+                         ry < c->refine_hi[1] && rz >= c->refine_lo[2] && rz < c->refine_hi[2];
+        L.rinfo[2 * r] = ref;
+        L.rinfo[2 * r + 1] = (int32_t)leaf.size();
+        if (!ref) {
+          leaf.push_back({0, rx, ry, rz});
+        } else {
+          for (int ch = 0; ch < 8; ++ch)
+            leaf.push_back({1, 2 * rx + (ch & 1), 2 * ry + ((ch >> 1) & 1), 2 * rz + (ch >> 2)});
+        }
+      }
+  L.nleaf = (int)leaf.size();
+  L.binfo.assign((size_t)L.nleaf * kLeafInts, 0);
+  auto refined = [&](const int r3[3]) { return L.rinfo[2 * (r3[0] + L.nr[0] * (r3[1] + L.nr[1] * r3[2]))]; };
+  auto first = [&](const int r3[3]) { return L.rinfo[2 * (r3[0] + L.nr[0] * (r3[1] + L.nr[1] * r3[2])) + 1]; };
+  for (int q = 0; q < L.nleaf; ++q) {
+    const int lev = leaf[q][0];
+    int32_t* b = &L.binfo[(size_t)q * kLeafInts];
+    b[0] = lev;
+    for (int d = 0; d < 3; ++d) b[7 + d] = leaf[q][1 + d];
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1;
+      int l[3] = {leaf[q][1], leaf[q][2], leaf[q][3]};
+      const int nl = L.nr[d] << lev;
+      l[d] += (f & 1) ? 1 : -1;
+      if (l[d] < 0 || l[d] >= nl) {
+        if (c->bc[d][0] != HY_BC_PERIODIC) { b[1 + f] = -1; continue; }
+        l[d] = (l[d] + nl) % nl;
+      }
+      const int r3[3] = {l[0] >> lev, l[1] >> lev, l[2] >> lev};
+      const bool fine_there = refined(r3) != 0;
+      if (fine_there == (lev == 1)) {  // same level
+        b[1 + f] = lev == 0 ? first(r3) : first(r3) + (l[0] & 1) + 2 * (l[1] & 1) + 4 * (l[2] & 1);
+      } else {                          // level change: a slab
+        b[1 + f] = L.nleaf + L.nvirt++;
+        L.vinfo.push_back(q);
+        L.vinfo.push_back(f);
+        if (lev == 0) {
+          L.cfinfo.push_back(q);
+          L.cfinfo.push_back(f);
+          ++L.ncf;
+        }
+      }
+    }
+  }
+}
+
+// Blocks per register: leaves plus slabs with refinement, else the root grid.
+int64_t register_blocks(const hy_config* c) {
+  if (!has_refine(c)) return (int64_t)(c->n[0] / c->block[0]) * (c->n[1] / c->block[1]) * (c->n[2] / c->block[2]);
+  SmrLayout L;
+  build_smr(c, L);
+  return (int64_t)L.nleaf + L.nvirt;
+}
+
 size_t reg_bytes(const hy_config* c) {
-  return align256((size_t)c->n[0] * c->n[1] * c->n[2] * 5 * sizeof(double));
+  const size_t vs = (size_t)c->block[0] * c->block[1] * c->block[2];
+  return align256((size_t)register_blocks(c) * vs * 5 * sizeof(double));
+}
+
+// Refinement tables in the workspace: leaf, slab, root and coarse-face tables.
+size_t smr_bytes(const hy_config* c, const SmrLayout* L) {
+  if (!has_refine(c)) return 0;
+  SmrLayout own;
+  if (!L) {
+    build_smr(c, own);
+    L = &own;
+  }
+  return align256(L->binfo.size() * 4) + align256(L->vinfo.size() * 4 + 4) +
+         align256(L->rinfo.size() * 4) + align256(L->cfinfo.size() * 4 + 4);
 }
 
 size_t flag_bytes(const hy_config* c) {
@@ -143,7 +253,7 @@ void default_launch(const hy_problem* p, int* variant, int* kc) {
   int tx, ty;
   stage_variant_shape(v, &tx, &ty);
   const int64_t cols = (int64_t)((bx + tx - 1) / tx) * ((p->cfg.block[1] + ty - 1) / ty);
-  const int64_t nb = (int64_t)p->nblk[0] * p->nblk[1] * p->nblk[2];
+  const int64_t nb = p->hp.nblocks;
   // enough tiles to fill the chip several times over; small problems march
   // through short z-chunks (down to one plane) rather than leave CUs idle
   int k = bz;
@@ -217,7 +327,7 @@ hy_status launch_group(hy_problem* const* ps, const std::vector<int>& act, const
       e.flags = flags;
       e.seq = (uint32_t)(p->hp.nstages * step_of[q] + stage - 1);
       e.stage = stage;
-      tiles += (int64_t)p->nblk[0] * p->nblk[1] * p->nblk[2] * e.ntx * e.nty * e.ntz;
+      tiles += (int64_t)p->hp.nblocks * e.ntx * e.nty * e.ntz;
     }
     if (tiles > 0x7fffffff) return fail(HY_ERR_ARG, "too many tiles in one launch");
     a.ntiles = (int32_t)tiles;
@@ -307,6 +417,9 @@ hy_status run_batch(hy_problem* const* ps, const int32_t* nsteps, int32_t n, hip
             act.push_back(q);
             by_kind[rk_stage_kind(ps[q]->hp, stage) - 1].push_back(q);
           }
+        for (int q : act)  // ghost slabs across level changes, from this stage's source
+          if (ps[q]->hp.nvirt > 0) HY_HIP(launch_smr_ghost(ps[q]->dp, stage, ps[q]->ng, ps[q]->hp.nvirt,
+                                                          ps[q]->cfg.block, s));
         for (int kind = 1; kind <= 2; ++kind) {
           st = launch_group(ps, by_kind[kind - 1], pl, stage, kind, step_of, flags, s);
           if (st != HY_OK) return st;
@@ -315,6 +428,15 @@ hy_status run_batch(hy_problem* const* ps, const int32_t* nsteps, int32_t n, hip
           st = launch_fix(ps, act, pl, stage, step_of, s);
           if (st != HY_OK) return st;
         }
+        for (int q : act)  // coarse faces next to finer leaves take the fine fluxes
+          if (ps[q]->hp.ncf > 0) {
+            const hy_problem* pq = ps[q];
+            const int last = stage == pq->hp.nstages;
+            const int parity = (int)(step_of[q] & 1);
+            HY_HIP(launch_smr_flux(pl.recon, pl.prec, pq->dp, stage, parity, last, pq->hp.ncf,
+                                   pq->cfg.block, s));
+            if (last) HY_HIP(launch_smr_dt(pq->dp, pq->ncell, parity ^ 1, s));
+          }
         st = launch_combines(ps, act, stage, step_of, s);
         if (st != HY_OK) return st;
       }
@@ -385,7 +507,38 @@ size_t hy_workspace_bytes(const hy_config* cfg) {
     g_err = msg;
     return 0;
   }
-  return (size_t)kHeaderBytes + (size_t)registers_of(cfg) * reg_bytes(cfg) + flag_bytes(cfg);
+  return (size_t)kHeaderBytes + (size_t)registers_of(cfg) * reg_bytes(cfg) + flag_bytes(cfg) +
+         smr_bytes(cfg, nullptr);
+}
+
+int32_t hy_leaves(const hy_config* cfg, int32_t* out) {
+  std::string msg;
+  if (!validate(cfg, msg)) {
+    g_err = msg;
+    return -1;
+  }
+  if (!has_refine(cfg)) {
+    const int nr[3] = {cfg->n[0] / cfg->block[0], cfg->n[1] / cfg->block[1], cfg->n[2] / cfg->block[2]};
+    int32_t q = 0;
+    for (int z = 0; z < nr[2]; ++z)
+      for (int y = 0; y < nr[1]; ++y)
+        for (int x = 0; x < nr[0]; ++x, ++q)
+          if (out) {
+            out[4 * q] = 0;
+            out[4 * q + 1] = x;
+            out[4 * q + 2] = y;
+            out[4 * q + 3] = z;
+          }
+    return q;
+  }
+  SmrLayout L;
+  build_smr(cfg, L);
+  if (out)
+    for (int q = 0; q < L.nleaf; ++q) {
+      out[4 * q] = L.binfo[(size_t)q * kLeafInts];
+      for (int d = 0; d < 3; ++d) out[4 * q + 1 + d] = L.binfo[(size_t)q * kLeafInts + 7 + d];
+    }
+  return L.nleaf;
 }
 
 hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_problem** out) {
@@ -452,6 +605,36 @@ hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_prob
   h.fofc_total = &p->dc->fofc_total;
   h.nstages = stages_of(cfg);
   for (int st = 1; st <= h.nstages; ++st) h.rk[st - 1] = rk_stage_of(h, st);
+  SmrLayout L;
+  if (has_refine(cfg)) {
+    build_smr(cfg, L);
+    if (L.nvirt > 65535 || L.ncf > 65535) {
+      delete p;
+      return fail(HY_ERR_ARG, "refined box has too many faces at a level change (max 65535)");
+    }
+    char* t = p->ws + kHeaderBytes + (size_t)nreg * reg_bytes(cfg) + flag_bytes(cfg);
+    h.binfo = (const int32_t*)t;
+    t += align256(L.binfo.size() * 4);
+    h.vinfo = (const int32_t*)t;
+    t += align256(L.vinfo.size() * 4 + 4);
+    h.rinfo = (const int32_t*)t;
+    t += align256(L.rinfo.size() * 4);
+    h.cfinfo = (const int32_t*)t;
+    h.nvirt = L.nvirt;
+    h.ncf = L.ncf;
+    for (int d = 0; d < 3; ++d) h.nroot[d] = L.nr[d];
+    h.nblocks = L.nleaf;
+    p->ncell = (int64_t)L.nleaf * h.vstride;
+    const std::pair<const int32_t*, const std::vector<int32_t>*> tabs[4] = {
+        {h.binfo, &L.binfo}, {h.vinfo, &L.vinfo}, {h.rinfo, &L.rinfo}, {h.cfinfo, &L.cfinfo}};
+    for (const auto& tb : tabs)
+      if (!tb.second->empty() &&
+          hipMemcpy((void*)tb.first, tb.second->data(), tb.second->size() * 4, hipMemcpyHostToDevice) !=
+              hipSuccess) {
+        delete p;
+        return fail(HY_ERR_HIP, "refinement table upload failed");
+      }
+  }
 
   unsigned char hdr[kHeaderBytes];
   std::memset(hdr, 0, sizeof hdr);
@@ -477,11 +660,16 @@ hy_status hy_set_state(hy_problem* p, const double* U, int where, void* stream) 
   hipStream_t s = (hipStream_t)stream;
   const double* src = U;
   const size_t bytes = (size_t)p->ncell * 5 * sizeof(double);
-  if (where != HY_DEVICE) {
-    HY_HIP(hipMemcpyAsync(p->hp.V, U, bytes, hipMemcpyHostToDevice, s));
-    src = p->hp.V;
+  if (p->hp.binfo) {  // refined mesh: leaf-major, the register's own layout
+    HY_HIP(hipMemcpyAsync(p->hp.U, U, bytes,
+                          where == HY_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  } else {
+    if (where != HY_DEVICE) {
+      HY_HIP(hipMemcpyAsync(p->hp.V, U, bytes, hipMemcpyHostToDevice, s));
+      src = p->hp.V;
+    }
+    HY_HIP(launch_scatter(p->dp, src, p->hp.U, p->ncell * 5, 1, s));
   }
-  HY_HIP(launch_scatter(p->dp, src, p->hp.U, p->ncell * 5, 1, s));
   const int slot = (int)(p->steps & 1);
   HY_HIP(launch_reset(p->dp, slot ^ 1, 0, s));  // the slot the next step reduces into
   HY_HIP(launch_reset(p->dp, slot, 1, s));
@@ -497,7 +685,10 @@ hy_status hy_get_state(hy_problem* p, double* U, int where, void* stream) {
     return fail(HY_ERR_ARG, "bad buffer location");
   hipStream_t s = (hipStream_t)stream;
   const size_t bytes = (size_t)p->ncell * 5 * sizeof(double);
-  if (where == HY_DEVICE) {
+  if (p->hp.binfo) {
+    HY_HIP(hipMemcpyAsync(U, p->hp.U, bytes,
+                          where == HY_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  } else if (where == HY_DEVICE) {
     HY_HIP(launch_scatter(p->dp, p->hp.U, U, p->ncell * 5, 0, s));
   } else {
     HY_HIP(launch_scatter(p->dp, p->hp.U, p->hp.V, p->ncell * 5, 0, s));

@@ -49,7 +49,18 @@ struct DevProblem {
   int32_t fofc;              // 1: first-order flux correction enabled
   int32_t nstages;           // SSP-RK stages per step: 1, 2, 3 or 10 (RK4)
   RkStage rk[kMaxStages];    // rk_stage_of(*this, s) at [s - 1], filled at creation
+  // Static refinement (all null / 0 without it). nblocks counts leaves; each
+  // register holds nblocks + nvirt blocks, the extra ones ghost slabs.
+  const int32_t* binfo;      // per leaf kLeafInts: level, neighbour per face
+                             // (-x,+x,-y,+y,-z,+z: leaf, nblocks + slab, or -1)
+  const int32_t* vinfo;      // per slab 2: owner leaf, face (2 d + side)
+  const int32_t* rinfo;      // per root block 2: refined, leaf or first child
+  const int32_t* cfinfo;     // per coarse face next to finer leaves 2: leaf, face
+  int32_t nvirt, ncf;
+  int32_t nroot[3];          // root blocks per axis
 };
+
+constexpr int kLeafInts = 12;  // level, neighbour per face (6), x, y, z at its level, 2 unused
 
 // The stage table (Sec. 3: low-storage SSP-RK of the Ketcheson family).
 //  RK1: U -> V, then V is copied to U.

@@ -28,6 +28,8 @@
 // step are always FP64. The library is built with -ffp-contract=off so every
 // instantiation performs identical per-cell arithmetic; FMAs are written out
 // where wanted.
+#include <algorithm>
+
 #include "hy_internal.h"
 
 namespace hy {
@@ -357,11 +359,20 @@ __device__ __forceinline__ double cell_dt(const Floors& fl, double gamma, double
   return m;
 }
 
+// Cell widths of block m (half the root widths on level 1).
+__device__ __forceinline__ void block_dx(const DevProblem& P, int64_t m, double dx[3]) {
+  const double s = (P.binfo && P.binfo[m * kLeafInts] != 0) ? 0.5 : 1.0;
+  dx[0] = P.dx[0] * s;
+  dx[1] = P.dx[1] * s;
+  dx[2] = P.dx[2] * s;
+}
+
 // ------------------------------------------------------- block geometry
 struct Geo {
   int bx, by, bz;
   int m;       // this tile's block
   int nb[6];   // neighbour block per face (-x,+x,-y,+y,-z,+z); -1 = outflow
+  int lev;     // refinement level (0 without refinement)
   int64_t bstride, vstride;
 };
 
@@ -372,6 +383,14 @@ __device__ __forceinline__ void geo_init(Geo& g, const DevProblem& P, int m) {
   g.m = m;
   g.bstride = P.bstride;
   g.vstride = P.vstride;
+  g.lev = 0;
+  if (P.binfo) {  // refined mesh: the leaf table (a slab stands in for a level change)
+    const int32_t* b = P.binfo + (int64_t)m * kLeafInts;
+    g.lev = b[0];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) g.nb[f] = b[1 + f];
+    return;
+  }
   const int nbx = P.nbx, nby = P.nby, nbz = P.nbz;
   const int mx = m % nbx, t = m / nbx, my = t % nby, mz = t / nby;
   const int sxy = nbx * nby;
@@ -617,7 +636,9 @@ k_stage(const StageArgs a) {
     const Gas<T> gas{T(gamma), T(gm1), T((gamma + 1.0) / (2.0 * gamma))};
     const Floors fl{P.rho_floor, P.p_floor / gm1};
     const double dt = P.cfl * __longlong_as_double((long long)P.dtmin[E.parity]);
-    const double idx = 1.0 / P.dx[0], idy = 1.0 / P.dx[1], idz = 1.0 / P.dx[2];
+    const double dsc = geo.lev ? 0.5 : 1.0;
+    const double dxb[3] = {P.dx[0] * dsc, P.dx[1] * dsc, P.dx[2] * dsc};
+    const double idx = 1.0 / dxb[0], idy = 1.0 / dxb[1], idz = 1.0 / dxb[2];
     const bool count = (E.flags & 1) != 0;
 
     // the slot this step reduces into; a one-stage step has no earlier
@@ -953,7 +974,7 @@ k_stage(const StageArgs a) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(unew[v], Out + off + v * vs);
         }
-        if (last) mydt = fmin(mydt, cell_dt(fl, gamma, gm1, P.dx, unew));
+        if (last) mydt = fmin(mydt, cell_dt(fl, gamma, gm1, dxb, unew));
       }
     }
 
@@ -1174,9 +1195,10 @@ __global__ void __launch_bounds__(256) k_fofc_dt(const FixArgs a) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x) {
     const int64_t m = c / P.vstride, rr = c - m * P.vstride;
-    double u[5];
+    double u[5], dxb[3];
     load5c(Un, m * P.bstride + rr, P.vstride, u);
-    mydt = fmin(mydt, cell_dt(fl, gamma, gm1, P.dx, u));
+    block_dx(P, m, dxb);
+    mydt = fmin(mydt, cell_dt(fl, gamma, gm1, dxb, u));
   }
   unsigned long long b = (unsigned long long)__double_as_longlong(mydt);
   for (int s = kWave / 2; s > 0; s >>= 1) {
@@ -1215,6 +1237,220 @@ __global__ void __launch_bounds__(256) k_combine(const FixArgs a, int op) {
   }
 }
 
+// ------------------------------------------------------ static refinement
+// A refined mesh's ghost slabs hold the state's representation at the slab
+// owner's level, at the ghost cell's global index (periodic wrap at that
+// level; an outflow face has no slab):
+//  level 0, coarse cell I: the coarse leaf's cell, or in a refined root the
+//    mean of its 8 fine cells, summed in pairs along x, then y, then z;
+//  level 1, fine cell i: the fine leaf's cell, or in an unrefined root the
+//    coarse value at floor(i/2) plus, per axis, a quarter of the minmod of the
+//    two level-0 differences next to it, signed towards the fine cell.
+__device__ __forceinline__ int wrap_or_clamp(int c, int n, int periodic) {
+  if (c < 0) return periodic ? c + n : 0;
+  if (c >= n) return periodic ? c - n : n - 1;
+  return c;
+}
+
+// All 5 variables of level-1 cell (i,j,k) inside a refined root.
+__device__ void smr_fine5(const DevProblem& P, const double* S, int i, int j, int k, double u[5]) {
+  const int lx = i / P.bx, ly = j / P.by, lz = k / P.bz;
+  const int r = (lx >> 1) + P.nroot[0] * ((ly >> 1) + P.nroot[1] * (lz >> 1));
+  const int q = P.rinfo[2 * r + 1] + (lx & 1) + 2 * (ly & 1) + 4 * (lz & 1);
+  load5c(S, (int64_t)q * P.bstride + ((int64_t)(k - lz * P.bz) * P.by + (j - ly * P.by)) * P.bx + (i - lx * P.bx),
+         P.vstride, u);
+}
+
+__device__ void smr_level0(const DevProblem& P, const double* S, int I, int J, int K, double u[5]) {
+  const int rx = I / P.bx, ry = J / P.by, rz = K / P.bz;
+  const int r = rx + P.nroot[0] * (ry + P.nroot[1] * rz);
+  if (!P.rinfo[2 * r]) {
+    load5c(S, (int64_t)P.rinfo[2 * r + 1] * P.bstride +
+               ((int64_t)(K - rz * P.bz) * P.by + (J - ry * P.by)) * P.bx + (I - rx * P.bx),
+           P.vstride, u);
+    return;
+  }
+  double f[8][5];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) smr_fine5(P, S, 2 * I + (c & 1), 2 * J + ((c >> 1) & 1), 2 * K + (c >> 2), f[c]);
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+    u[v] = (((f[0][v] + f[1][v]) + (f[2][v] + f[3][v])) + ((f[4][v] + f[5][v]) + (f[6][v] + f[7][v]))) * 0.125;
+}
+
+__device__ __forceinline__ double minmod2(double a, double b) {
+  if (!(a * b > 0.0)) return 0.0;
+  return fabs(a) < fabs(b) ? a : b;
+}
+
+__device__ void smr_level1(const DevProblem& P, const double* S, int i, int j, int k, double u[5]) {
+  const int r = i / (2 * P.bx) + P.nroot[0] * (j / (2 * P.by) + P.nroot[1] * (k / (2 * P.bz)));
+  if (P.rinfo[2 * r]) {
+    smr_fine5(P, S, i, j, k, u);
+    return;
+  }
+  const int c[3] = {i >> 1, j >> 1, k >> 1};
+  const int odd[3] = {i & 1, j & 1, k & 1};
+  const int n0[3] = {P.nroot[0] * P.bx, P.nroot[1] * P.by, P.nroot[2] * P.bz};
+  double C[5], t[3][5];
+  smr_level0(P, S, c[0], c[1], c[2], C);
+  for (int d = 0; d < 3; ++d) {
+    int lo[3] = {c[0], c[1], c[2]}, hi[3] = {c[0], c[1], c[2]};
+    lo[d] = wrap_or_clamp(c[d] - 1, n0[d], P.periodic[d]);
+    hi[d] = wrap_or_clamp(c[d] + 1, n0[d], P.periodic[d]);
+    double a[5], b[5];
+    smr_level0(P, S, lo[0], lo[1], lo[2], a);
+    smr_level0(P, S, hi[0], hi[1], hi[2], b);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double sl = minmod2(C[v] - a[v], b[v] - C[v]);
+      t[d][v] = odd[d] ? sl : -sl;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) u[v] = C[v] + 0.25 * ((t[0][v] + t[1][v]) + t[2][v]);
+}
+
+// Fill every ghost slab of one problem from the stage's source register, one
+// thread per slab cell (all 5 variables). Slab blocks follow the leaves in the
+// same register; the slab cell sits where ghost_local looks for it (the
+// neighbour block's frame), so the stage kernel reads it unchanged.
+__global__ void __launch_bounds__(256) k_smr_ghost(const DevProblem* __restrict__ Pp, int stage, int ng) {
+  const DevProblem& P = *Pp;
+  double* S = const_cast<double*>(P.rk[stage - 1].src);
+  const int vb = blockIdx.y;
+  const int own = P.vinfo[2 * vb], f = P.vinfo[2 * vb + 1];
+  const int d = f >> 1, side = f & 1;
+  const int32_t* b = P.binfo + (int64_t)own * kLeafInts;
+  const int lev = b[0];
+  const int bd[3] = {P.bx, P.by, P.bz};
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+  const int area = bd[t1] * bd[t2];
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ng * area; c += gridDim.x * blockDim.x) {
+    const int l = c / area, rem = c - l * area;
+    const int a2 = rem / bd[t1], a1 = rem - a2 * bd[t1];
+    int g3[3], s3[3];
+    g3[t1] = b[7 + t1] * bd[t1] + a1;
+    g3[t2] = b[7 + t2] * bd[t2] + a2;
+    const int nl = (P.nroot[d] * bd[d]) << lev;
+    g3[d] = wrap_or_clamp(side ? b[7 + d] * bd[d] + bd[d] + l : b[7 + d] * bd[d] - 1 - l, nl, P.periodic[d]);
+    double u[5];
+    if (lev == 0) smr_level0(P, S, g3[0], g3[1], g3[2], u);
+    else smr_level1(P, S, g3[0], g3[1], g3[2], u);
+    s3[t1] = a1;
+    s3[t2] = a2;
+    s3[d] = side ? l : bd[d] - 1 - l;
+    double* o = S + (int64_t)(P.nblocks + vb) * P.bstride + ((int64_t)s3[2] * P.by + s3[1]) * P.bx + s3[0];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) o[v * P.vstride] = u[v];
+  }
+}
+
+// Flux correction along direction `dir` (Sec. 2: the flux through a coarse
+// face shared with finer blocks is the finer blocks' flux): for each coarse
+// face next to 4 fine faces (cfinfo), the coarse cell adds
+// c dt (F_coarse - mean F_fine) / dx on an upper face, the opposite on a
+// lower one, both fluxes recomputed from the stage's source exactly as the
+// stage kernel formed them. One launch per direction, so no cell is updated
+// twice within a launch. With `last`, the first launch also clears the
+// time-step slot that k_smr_dt then fills from the corrected state.
+template <int RECON, typename T>
+__global__ void __launch_bounds__(256) k_smr_flux(const DevProblem* __restrict__ Pp, int stage, int parity,
+                                                  int dir, int last) {
+  const DevProblem& P = *Pp;
+  if (last && dir == 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+    P.dtmin[parity ^ 1] = kInfBits;
+  const int e = blockIdx.y;
+  const int q = P.cfinfo[2 * e], f = P.cfinfo[2 * e + 1];
+  const int d = f >> 1, side = f & 1;
+  if (d != dir) return;
+  const RkStage& rs = P.rk[stage - 1];
+  const double* __restrict__ S = rs.src;
+  double* Out = rs.dst;
+  const double gamma = P.gamma, gm1 = gamma - 1.0;
+  const Gas<T> gas{T(gamma), T(gm1), T((gamma + 1.0) / (2.0 * gamma))};
+  const Floors fl{P.rho_floor, P.p_floor / gm1};
+  const double cst = rs.c * (P.cfl * __longlong_as_double((long long)P.dtmin[parity]));
+  const double idc = 1.0 / P.dx[d];  // the coarse leaf is on level 0
+  const int bd[3] = {P.bx, P.by, P.bz};
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+  const int32_t* bq = P.binfo + (int64_t)q * kLeafInts;
+  const int n1 = 2 * P.nroot[d] * bd[d];
+  Geo gc;
+  geo_init(gc, P, q);
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < bd[t1] * bd[t2]; c += gridDim.x * blockDim.x) {
+    const int a2 = c / bd[t1], a1 = c - a2 * bd[t1];
+    int cf[3];
+    cf[d] = side ? bd[d] : 0;  // face_pair's cell index: the face's upper cell
+    cf[t1] = a1;
+    cf[t2] = a2;
+    T fc[5], unused[5];
+    face_pair<RECON, T>(gc, fl, gas, S, d, cf[0], cf[1], cf[2], fc, unused);
+    double ff[4][5];
+#pragma unroll 1
+    for (int h = 0; h < 4; ++h) {
+      int g3[3];
+      g3[d] = side ? 2 * (bq[7 + d] + 1) * bd[d] : 2 * bq[7 + d] * bd[d] - 1;
+      g3[d] = (g3[d] + n1) % n1;
+      g3[t1] = 2 * (bq[7 + t1] * bd[t1] + a1) + (h & 1);
+      g3[t2] = 2 * (bq[7 + t2] * bd[t2] + a2) + (h >> 1);
+      const int lx = g3[0] / bd[0], ly = g3[1] / bd[1], lz = g3[2] / bd[2];
+      const int r = (lx >> 1) + P.nroot[0] * ((ly >> 1) + P.nroot[1] * (lz >> 1));
+      const int qf = P.rinfo[2 * r + 1] + (lx & 1) + 2 * (ly & 1) + 4 * (lz & 1);
+      int lf[3] = {g3[0] - lx * bd[0], g3[1] - ly * bd[1], g3[2] - lz * bd[2]};
+      lf[d] = side ? 0 : bd[d];
+      Geo gf;
+      geo_init(gf, P, qf);
+      T fo[5];
+      face_pair<RECON, T>(gf, fl, gas, S, d, lf[0], lf[1], lf[2], fo, unused);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) ff[h][v] = (double)fo[v];
+    }
+    int cc[3];
+    cc[d] = side ? bd[d] - 1 : 0;
+    cc[t1] = a1;
+    cc[t2] = a2;
+    const int64_t off = (int64_t)q * P.bstride + ((int64_t)cc[2] * P.by + cc[1]) * P.bx + cc[0];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double mean = ((ff[0][v] + ff[1][v]) + (ff[2][v] + ff[3][v])) * 0.25;
+      const double dl = side ? ((double)fc[v] - mean) * idc : (mean - (double)fc[v]) * idc;
+      Out[off + v * P.vstride] += cst * dl;
+    }
+  }
+}
+
+// Time step of the corrected new state of a refined mesh into dtmin[slot].
+__global__ void __launch_bounds__(256) k_smr_dt(const DevProblem* __restrict__ Pp, int slot) {
+  const DevProblem& P = *Pp;
+  const double gamma = P.gamma, gm1 = gamma - 1.0;
+  const Floors fl{P.rho_floor, P.p_floor / gm1};
+  const int64_t ncell = (int64_t)P.nblocks * P.vstride;
+  const double* __restrict__ Un = P.rk[P.nstages - 1].dst;
+  double mydt = __longlong_as_double((long long)kInfBits);
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = c / P.vstride, rr = c - m * P.vstride;
+    double u[5], dxb[3];
+    load5c(Un, m * P.bstride + rr, P.vstride, u);
+    block_dx(P, m, dxb);
+    mydt = fmin(mydt, cell_dt(fl, gamma, gm1, dxb, u));
+  }
+  unsigned long long b = (unsigned long long)__double_as_longlong(mydt);
+  for (int s = kWave / 2; s > 0; s >>= 1) {
+    const unsigned long long o = __shfl_xor(b, s, kWave);
+    b = o < b ? o : b;
+  }
+  __shared__ unsigned long long red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long mn = red[0];
+    for (int w = 1; w < 4; ++w) mn = red[w] < mn ? red[w] : mn;
+    atomicMin(P.dtmin + slot, mn);
+  }
+}
+
 // ------------------------------------------------------------ small kernels
 // Time step of a stored state into dtmin[slot] (after k_reset_dt).
 __global__ void __launch_bounds__(256) k_dt(const DevProblem* __restrict__ Pp, int slot, int flags) {
@@ -1227,12 +1463,13 @@ __global__ void __launch_bounds__(256) k_dt(const DevProblem* __restrict__ Pp, i
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x) {
     const int64_t m = c / P.vstride, rr = c - m * P.vstride;
-    double u[5];
+    double u[5], dxb[3];
     load5c(P.U, m * P.bstride + rr, P.vstride, u);
     double w[5];
     int h = 0;
     c2p(fl, u, w, h, bad);
-    mydt = fmin(mydt, cell_dt(fl, gamma, gm1, P.dx, u));
+    block_dx(P, m, dxb);
+    mydt = fmin(mydt, cell_dt(fl, gamma, gm1, dxb, u));
   }
   if ((flags & 1) && bad) atomicOr(P.err, 1u);
   unsigned long long b = (unsigned long long)__double_as_longlong(mydt);
@@ -1389,6 +1626,41 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) 
   if (g > 65536) g = 65536;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)g), dim3(256), 0, s, (const u32x4*)src, (u32x4*)dst, n);
+  return hipGetLastError();
+}
+
+
+hipError_t launch_smr_ghost(const DevProblem* p, int stage, int ng, int nvirt, const int32_t block[3],
+                            hipStream_t s) {
+  const int area = std::max(block[1] * block[2], std::max(block[0] * block[2], block[0] * block[1]));
+  const int gx = std::max(1, std::min((ng * area + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_smr_ghost, dim3(gx, nvirt), dim3(256), 0, s, p, stage, ng);
+  return hipGetLastError();
+}
+
+hipError_t launch_smr_flux(int recon, int prec, const DevProblem* p, int stage, int parity, int last,
+                           int ncf, const int32_t block[3], hipStream_t s) {
+  using K = void (*)(const DevProblem*, int, int, int, int);
+  static const K tab[4][2] = {{k_smr_flux<0, double>, k_smr_flux<0, float>},
+                              {k_smr_flux<1, double>, k_smr_flux<1, float>},
+                              {k_smr_flux<2, double>, k_smr_flux<2, float>},
+                              {k_smr_flux<3, double>, k_smr_flux<3, float>}};
+  if (recon < 0 || recon > 3 || prec < 0 || prec > 1) return hipErrorInvalidValue;
+  const int area = std::max(block[1] * block[2], std::max(block[0] * block[2], block[0] * block[1]));
+  const int gx = std::max(1, std::min((area + 255) / 256, 1024));
+  for (int dir = 0; dir < 3; ++dir) {
+    hipLaunchKernelGGL(tab[recon][prec], dim3(gx, ncf), dim3(256), 0, s, p, stage, parity, dir, last);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_smr_dt(const DevProblem* p, int64_t ncell, int slot, hipStream_t s) {
+  int64_t g = (ncell + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_smr_dt, dim3((unsigned)g), dim3(256), 0, s, p, slot);
   return hipGetLastError();
 }
 

@@ -42,6 +42,8 @@ class HyConfig(_c.Structure):
         ("rk", _c.c_int32),
         ("rho_floor", _c.c_double),
         ("p_floor", _c.c_double),
+        ("refine_lo", _c.c_int32 * 3),
+        ("refine_hi", _c.c_int32 * 3),
     ]
 
 
@@ -51,6 +53,7 @@ _i64p = _c.POINTER(_c.c_int64)
 
 SIGNATURES = {
     "hy_workspace_bytes": ([_CP], _c.c_size_t),
+    "hy_leaves": ([_CP, _i32p], _c.c_int32),
     "hy_create": ([_CP, _vp, _c.c_size_t, _c.POINTER(_vp)], _c.c_int),
     "hy_set_state": ([_vp, _vp, _c.c_int, _vp], _c.c_int),
     "hy_get_state": ([_vp, _vp, _c.c_int, _vp], _c.c_int),
@@ -136,7 +139,24 @@ def make_config(pb) -> HyConfig:
     c.rk = int(getattr(pb, "rk", 2))
     c.rho_floor = float(pb.rho_floor)
     c.p_floor = float(pb.p_floor)
+    ref = getattr(pb, "refine", None)
+    if ref is not None:
+        for d in range(3):
+            c.refine_lo[d] = int(ref[0][d])
+            c.refine_hi[d] = int(ref[1][d])
     return c
+
+
+def leaves(pb) -> np.ndarray:
+    """Leaf blocks of the problem's mesh as int32 [leaf][level, x, y, z]
+    (the order of a refined problem's leaf-major state)."""
+    c = make_config(pb)
+    n = lib().hy_leaves(_c.byref(c), None)
+    if n < 0:
+        raise HydroError(HY_ERR_ARG, last_error())
+    out = np.zeros((n, 4), dtype=np.int32)
+    lib().hy_leaves(_c.byref(c), out.ctypes.data_as(_i32p))
+    return out
 
 
 def workspace_bytes(pb) -> int:
@@ -181,7 +201,11 @@ class Problem:
         with torch.cuda.device(dev):
             _check(lib().hy_create(_c.byref(self.cfg), _vp(self.ws_ptr), self.nbytes, _c.byref(h)))
         self.h = h
-        self.shape = (5, int(pb.n[2]), int(pb.n[1]), int(pb.n[0]))
+        if getattr(pb, "refine", None) is not None:  # leaf-major state
+            bx, by, bz = (int(b) for b in pb.block)
+            self.shape = (len(leaves(pb)), 5, bz, by, bx)
+        else:
+            self.shape = (5, int(pb.n[2]), int(pb.n[1]), int(pb.n[0]))
 
     # -- state ---------------------------------------------------------
     def set_state(self, U=None, stream=None):

@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -38,7 +40,7 @@ def test_workspace_bytes_and_validation_without_gpu():
     from paper_2409_16053_amd import problems as P
     pb = P.turbulence(N=16, seed=1, kmax=4).with_(block=(8, 8, 8))
     n = hy.workspace_bytes(pb)
-    assert n == 512 + 2 * ((16 ** 3 * 5 * 8 + 255) // 256 * 256)
+    assert n == 1024 + 2 * ((16 ** 3 * 5 * 8 + 255) // 256 * 256)
     with pytest.raises(hy.HydroError):
         hy.workspace_bytes(pb.with_(block=(5, 8, 8)))
     with pytest.raises(hy.HydroError):
@@ -62,3 +64,58 @@ def test_struct_layout_matches_header(tmp_path):
     assert vals[0] == ctypes.sizeof(hy.HyConfig)
     for f, off in zip(fields, vals[1:]):
         assert getattr(hy.HyConfig, f).offset == off, f
+
+
+# ------------------------------------------------------------- refined meshes
+def _slab_faces(lv, nr, periodic):
+    """Leaf faces whose neighbour region is at the other level, counted from
+    the leaf list alone (coarse ones separately)."""
+    have = {(int(L), int(x), int(y), int(z)) for L, x, y, z in lv}
+    nvirt = ncf = 0
+    for L, x, y, z in lv:
+        for d in range(3):
+            for s in (-1, 1):
+                l = [int(x), int(y), int(z)]
+                l[d] += s
+                n = nr[d] << int(L)
+                if not 0 <= l[d] < n:
+                    if not periodic:
+                        continue
+                    l[d] %= n
+                if (int(L), *l) not in have:
+                    nvirt += 1
+                    ncf += int(L) == 0
+    return nvirt, ncf
+
+
+@pytest.mark.parametrize("box,periodic", [(((1, 0, 1), (3, 2, 2)), True), (((0, 0, 0), (1, 1, 1)), False),
+                                          (((0, 0, 0), (4, 3, 2)), True), (((2, 1, 0), (3, 3, 2)), False)])
+def test_refined_leaves_and_workspace_without_gpu(box, periodic):
+    import oracle
+    from paper_2409_16053_amd import hy
+    from paper_2409_16053_amd import problems as P
+    pb = P.uniform(n=(32, 24, 16), rho=1.0, v=(0, 0, 0), p=1.0, bc=P.PERIODIC if periodic else P.OUTFLOW)
+    pb = pb.with_(block=(8, 8, 8), refine=box, rk=3)
+    lv = hy.leaves(pb)
+    assert np.array_equal(lv, oracle.smr_leaves(pb))
+    nvirt, ncf = _slab_faces(lv, (4, 3, 2), periodic)
+    a = lambda b: (b + 255) // 256 * 256
+    reg = a((len(lv) + nvirt) * 8 ** 3 * 5 * 8)
+    tables = a(len(lv) * 12 * 4) + a(nvirt * 2 * 4 + 4) + a(24 * 2 * 4) + a(ncf * 2 * 4 + 4)
+    assert hy.workspace_bytes(pb) == 1024 + 3 * reg + tables
+
+
+@pytest.mark.parametrize("bad", [dict(block=(9, 8, 8), n=(36, 24, 16)), dict(fofc=1),
+                                 dict(refine=((0, 0, 0), (5, 1, 1))), dict(recon=3, block=(4, 8, 8))])
+def test_refined_configuration_errors_without_gpu(bad):
+    # each case is valid without refinement and invalid with it (odd block,
+    # FOFC, box outside the root grid, block below twice the ghost depth)
+    from paper_2409_16053_amd import hy
+    from paper_2409_16053_amd import problems as P
+    pb = P.uniform(n=(32, 24, 16), rho=1.0, v=(0, 0, 0), p=1.0, bc=P.PERIODIC)
+    pb = pb.with_(block=(8, 8, 8), refine=((0, 0, 0), (1, 1, 1)))
+    assert hy.workspace_bytes(pb) > 0
+    if "refine" not in bad:
+        assert hy.workspace_bytes(pb.with_(refine=None, **bad)) > 0
+    with pytest.raises(hy.HydroError):
+        hy.workspace_bytes(pb.with_(**bad))
