@@ -376,6 +376,9 @@ struct Geo {
   int64_t bstride, vstride;
 };
 
+// UNIFORM: m is the same in every lane of the wave (the stage kernel's tile
+// block), which lets the leaf table's entries live in scalar registers.
+template <bool UNIFORM = false>
 __device__ __forceinline__ void geo_init(Geo& g, const DevProblem& P, int m) {
   g.bx = P.bx;
   g.by = P.by;
@@ -386,9 +389,9 @@ __device__ __forceinline__ void geo_init(Geo& g, const DevProblem& P, int m) {
   g.lev = 0;
   if (P.binfo) {  // refined mesh: the leaf table (a slab stands in for a level change)
     const int32_t* b = P.binfo + (int64_t)m * kLeafInts;
-    g.lev = b[0];
+    g.lev = UNIFORM ? __builtin_amdgcn_readfirstlane(b[0]) : b[0];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) g.nb[f] = b[1 + f];
+    for (int f = 0; f < 6; ++f) g.nb[f] = UNIFORM ? __builtin_amdgcn_readfirstlane(b[1 + f]) : b[1 + f];
     return;
   }
   const int nbx = P.nbx, nby = P.nby, nbz = P.nbz;
@@ -617,7 +620,7 @@ k_stage(const StageArgs a) {
     const int txi = r - tyi * E.ntx;
 
     Geo geo;
-    geo_init(geo, P, m);
+    geo_init<true>(geo, P, m);
     const int i0 = txi * TX, j0 = tyi * TY, k0 = tzi * E.kc;
     const int nxv = min(TX, geo.bx - i0), nyv = min(TY, geo.by - j0);
     const int kend = min(k0 + E.kc, geo.bz);
@@ -636,9 +639,11 @@ k_stage(const StageArgs a) {
     const Gas<T> gas{T(gamma), T(gm1), T((gamma + 1.0) / (2.0 * gamma))};
     const Floors fl{P.rho_floor, P.p_floor / gm1};
     const double dt = P.cfl * __longlong_as_double((long long)P.dtmin[E.parity]);
-    const double dsc = geo.lev ? 0.5 : 1.0;
-    const double dxb[3] = {P.dx[0] * dsc, P.dx[1] * dsc, P.dx[2] * dsc};
-    const double idx = 1.0 / dxb[0], idy = 1.0 / dxb[1], idz = 1.0 / dxb[2];
+    // a level-1 block has half the root widths: scaling by a power of two
+    // commutes with rounding (and with the minimum of the time step), so the
+    // root widths are used and the results scaled once
+    const double isc = geo.lev ? 2.0 : 1.0, dsc = geo.lev ? 0.5 : 1.0;
+    const double idx = (1.0 / P.dx[0]) * isc, idy = (1.0 / P.dx[1]) * isc, idz = (1.0 / P.dx[2]) * isc;
     const bool count = (E.flags & 1) != 0;
 
     // the slot this step reduces into; a one-stage step has no earlier
@@ -974,7 +979,7 @@ k_stage(const StageArgs a) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(unew[v], Out + off + v * vs);
         }
-        if (last) mydt = fmin(mydt, cell_dt(fl, gamma, gm1, dxb, unew));
+        if (last) mydt = fmin(mydt, dsc * cell_dt(fl, gamma, gm1, P.dx, unew));
       }
     }
 
