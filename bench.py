@@ -85,6 +85,10 @@ def main():
                     help="serve COUNT requests of the seeded Poisson stream (0: skip)")
     ap.add_argument("--skip-kh", action="store_true", help="skip the 512^3 PPM4 workload")
     ap.add_argument("--skip-schemes", action="store_true", help="skip WENO-Z/RK3 and PPM4 at 256^3")
+    ap.add_argument("--skip-refined", action="store_true",
+                    help="skip the statically refined 256^3 workload")
+    ap.add_argument("--refined-only", action="store_true",
+                    help="time only the statically refined workload (for profiling)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the 256^3 FP64 (and mixed) lines")
     ap.add_argument("--serve-budget-gb", default="16",
@@ -137,6 +141,11 @@ def main():
         g.close()
         sec = t1 - t0
         return dict(sec=sec, ms1=ms1, ms2=ms2, q=q, U=U, launch=launch)
+
+    if args.refined_only:
+        print(json.dumps({"refined": run_refined(run, hy, P, None, args.steps, cpu=not args.skip_cpu)}),
+              flush=True)
+        return
 
     log("timing FP64")
     r64 = run(P.FP64)
@@ -240,6 +249,8 @@ def main():
             out["schemes"] = run_schemes(run, pb, P, args.steps)
         if not args.skip_kh:
             out["kh512"] = run_kh512(run, P)
+        if not args.skip_refined:
+            out["refined"] = run_refined(run, hy, P, value, args.steps, cpu=not args.skip_cpu)
         if not args.no_batch:
             out["batch"] = run_batch_workload(hy, P, torch)
         if args.serve:
@@ -281,6 +292,42 @@ def run_schemes(run, pb, P, steps):
                 "value": pb.cells * steps / r["sec"], "unit": "cell-updates/s",
                 "ms_per_step": 1e3 * r["sec"] / steps, "launch": list(r["launch"])}
     return res
+
+
+def run_refined(run, hy, P, uniform_value, steps, cpu=True):
+    """The 256^3 turbulence mesh with its central 2^3 root blocks refined once
+    (120 leaf MeshBlocks of 64^3), FP64 and mixed: throughput over all leaf
+    cells, its ratio to the uniform headline rate per cell-update (the cost of
+    the ghost slabs, the flux correction and the extra time step), and the
+    reference solver's rate on one step of the same mesh."""
+    log("building the refined 256^3 turbulence mesh")
+    base, _ = P.workload_turbulence_256()
+    base = base.with_(refine=P.REFINED_BOX_256)
+    pb, _ = P.workload_turbulence_refined(hy.leaves(base))
+    lv = hy.leaves(pb)
+    out = {"workload": "turbulence 256^3 periodic, central 2^3 of 4^3 root blocks refined once: "
+                       f"{int((lv[:, 0] == 0).sum())} MeshBlocks of 64^3 on level 0, "
+                       f"{int((lv[:, 0] == 1).sum())} on level 1, PLM+HLLC, SSP-RK2",
+           "cells": pb.cells, "steps": steps}
+    for prec in (P.FP64, P.MIXED):
+        name = "fp64" if prec == P.FP64 else "mixed"
+        log(f"timing refined {name}")
+        r = run(prec, prob=pb, steps=steps)
+        out[name] = {"value": pb.cells * steps / r["sec"], "unit": "cell-updates/s",
+                     "ms_per_step": 1e3 * r["sec"] / steps, "launch": list(r["launch"])}
+    if uniform_value:
+        out["fp64"]["rate_vs_uniform"] = out["fp64"]["value"] / uniform_value
+    if cpu:
+        import oracle
+        oracle.build(force=False)
+        log("timing the CPU reference solver on one step of the refined mesh")
+        t0 = time.perf_counter()
+        oracle.advance(pb, 1)
+        t1 = time.perf_counter()
+        out["cpu_baseline"] = {"value": pb.cells / (t1 - t0), "unit": "cell-updates/s",
+                               "cores": oracle.get_threads(), "kind": "oracle",
+                               "sample": f"1 RK2 step of the refined mesh, {t1 - t0:.1f} s wall"}
+    return out
 
 
 def run_kh512(run, P):

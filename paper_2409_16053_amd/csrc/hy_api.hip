@@ -433,9 +433,8 @@ hy_status run_batch(hy_problem* const* ps, const int32_t* nsteps, int32_t n, hip
             const hy_problem* pq = ps[q];
             const int last = stage == pq->hp.nstages;
             const int parity = (int)(step_of[q] & 1);
-            HY_HIP(launch_smr_flux(pl.recon, pl.prec, pq->dp, stage, parity, last, pq->hp.ncf,
-                                   pq->cfg.block, s));
-            if (last) HY_HIP(launch_smr_dt(pq->dp, pq->ncell, parity ^ 1, s));
+            HY_HIP(launch_smr_flux(pl.recon, pl.prec, pq->dp, stage, parity, pq->hp.ncf, pq->cfg.block, s));
+            if (last) HY_HIP(launch_smr_dt(pq->dp, pq->hp.nblocks, pq->cfg.block, parity ^ 1, s));
           }
         st = launch_combines(ps, act, stage, step_of, s);
         if (st != HY_OK) return st;
@@ -608,9 +607,9 @@ hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_prob
   SmrLayout L;
   if (has_refine(cfg)) {
     build_smr(cfg, L);
-    if (L.nvirt > 65535 || L.ncf > 65535) {
+    if (L.nvirt > 65535 || L.ncf > 65535 || L.nleaf > 65535) {
       delete p;
-      return fail(HY_ERR_ARG, "refined box has too many faces at a level change (max 65535)");
+      return fail(HY_ERR_ARG, "refined mesh too large (max 65535 leaves and level-change faces)");
     }
     char* t = p->ws + kHeaderBytes + (size_t)nreg * reg_bytes(cfg) + flag_bytes(cfg);
     h.binfo = (const int32_t*)t;

@@ -559,6 +559,13 @@ __device__ __forceinline__ void face_flux(const Gas<T>& gas, const T* __restrict
   }
 }
 
+// A level-0 leaf with a ghost slab on some face (finer leaves across): the
+// flux correction changes its cells on those faces after each stage.
+__device__ __forceinline__ bool smr_cf_leaf(const Geo& g, int nblocks) {
+  return g.lev == 0 && (g.nb[0] >= nblocks || g.nb[1] >= nblocks || g.nb[2] >= nblocks ||
+                        g.nb[3] >= nblocks || g.nb[4] >= nblocks || g.nb[5] >= nblocks);
+}
+
 // -------------------------------------------------------------- the stage
 // A pointer that is the same in every lane, moved to scalar registers. The
 // compiler does not prove the stage's register pointers uniform (they come
@@ -643,6 +650,9 @@ k_stage(const StageArgs a) {
     // commutes with rounding (and with the minimum of the time step), so the
     // root widths are used and the results scaled once
     const double isc = geo.lev ? 2.0 : 1.0, dsc = geo.lev ? 0.5 : 1.0;
+    // the tiles of a coarse leaf next to finer ones leave the time step to
+    // k_smr_dt, which runs after the flux correction has changed the leaf
+    const bool last_dt = last && !(P.binfo && smr_cf_leaf(geo, P.nblocks));
     const double idx = (1.0 / P.dx[0]) * isc, idy = (1.0 / P.dx[1]) * isc, idz = (1.0 / P.dx[2]) * isc;
     const bool count = (E.flags & 1) != 0;
 
@@ -979,7 +989,7 @@ k_stage(const StageArgs a) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(unew[v], Out + off + v * vs);
         }
-        if (last) mydt = fmin(mydt, dsc * cell_dt(fl, gamma, gm1, P.dx, unew));
+        if (last_dt) mydt = fmin(mydt, dsc * cell_dt(fl, gamma, gm1, P.dx, unew));
       }
     }
 
@@ -988,7 +998,7 @@ k_stage(const StageArgs a) {
       if (hits) atomicAdd(P.floor_hits, (unsigned long long)hits);
       if (bad) atomicOr(P.err, 1u);
     }
-    if (last) {
+    if (last_dt) {
       unsigned long long b = (unsigned long long)__double_as_longlong(mydt);
 #pragma unroll
       for (int s = kWave / 2; s > 0; s >>= 1) {
@@ -1001,9 +1011,9 @@ k_stage(const StageArgs a) {
         unsigned long long mn = sRed[0];
         for (int wv = 1; wv < NWAVE; ++wv) mn = sRed[wv] < mn ? sRed[wv] : mn;
         atomicMin(P.dtmin + (E.parity ^ 1), mn);
-        if (loc == 0) *P.time = *P.time + dt;
       }
     }
+    if (last && loc == 0 && tid == 0) *P.time = *P.time + dt;
     __syncthreads();  // LDS reuse by the next tile of this workgroup
   }
 }
@@ -1357,14 +1367,11 @@ __global__ void __launch_bounds__(256) k_smr_ghost(const DevProblem* __restrict_
 // c dt (F_coarse - mean F_fine) / dx on an upper face, the opposite on a
 // lower one, both fluxes recomputed from the stage's source exactly as the
 // stage kernel formed them. One launch per direction, so no cell is updated
-// twice within a launch. With `last`, the first launch also clears the
-// time-step slot that k_smr_dt then fills from the corrected state.
+// twice within a launch.
 template <int RECON, typename T>
 __global__ void __launch_bounds__(256) k_smr_flux(const DevProblem* __restrict__ Pp, int stage, int parity,
-                                                  int dir, int last) {
+                                                  int dir) {
   const DevProblem& P = *Pp;
-  if (last && dir == 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
-    P.dtmin[parity ^ 1] = kInfBits;
   const int e = blockIdx.y;
   const int q = P.cfinfo[2 * e], f = P.cfinfo[2 * e + 1];
   const int d = f >> 1, side = f & 1;
@@ -1425,33 +1432,36 @@ __global__ void __launch_bounds__(256) k_smr_flux(const DevProblem* __restrict__
   }
 }
 
-// Time step of the corrected new state of a refined mesh into dtmin[slot].
+// Time step of the corrected new state over the level-0 leaves next to finer
+// ones (the stage kernel left them out), into dtmin[slot]. One grid row per
+// leaf; the rows of other leaves return at once.
 __global__ void __launch_bounds__(256) k_smr_dt(const DevProblem* __restrict__ Pp, int slot) {
   const DevProblem& P = *Pp;
+  const int m = blockIdx.y;
+  Geo g;
+  geo_init(g, P, m);
+  if (!smr_cf_leaf(g, P.nblocks)) return;  // the whole workgroup
   const double gamma = P.gamma, gm1 = gamma - 1.0;
   const Floors fl{P.rho_floor, P.p_floor / gm1};
-  const int64_t ncell = (int64_t)P.nblocks * P.vstride;
   const double* __restrict__ Un = P.rk[P.nstages - 1].dst;
   double mydt = __longlong_as_double((long long)kInfBits);
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P.vstride;
        c += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t m = c / P.vstride, rr = c - m * P.vstride;
-    double u[5], dxb[3];
-    load5c(Un, m * P.bstride + rr, P.vstride, u);
-    block_dx(P, m, dxb);
-    mydt = fmin(mydt, cell_dt(fl, gamma, gm1, dxb, u));
+    double u[5];
+    load5c(Un, (int64_t)m * P.bstride + c, P.vstride, u);
+    mydt = fmin(mydt, cell_dt(fl, gamma, gm1, P.dx, u));  // level-0 widths
   }
   unsigned long long b = (unsigned long long)__double_as_longlong(mydt);
-  for (int s = kWave / 2; s > 0; s >>= 1) {
-    const unsigned long long o = __shfl_xor(b, s, kWave);
-    b = o < b ? o : b;
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const unsigned long long x = __shfl_xor(b, o, kWave);
+    b = x < b ? x : b;
   }
-  __shared__ unsigned long long red[4];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+  __shared__ unsigned long long red[256 / kWave];
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = b;
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long mn = red[0];
-    for (int w = 1; w < 4; ++w) mn = red[w] < mn ? red[w] : mn;
+    for (int w = 1; w < 256 / kWave; ++w) mn = red[w] < mn ? red[w] : mn;
     atomicMin(P.dtmin + slot, mn);
   }
 }
@@ -1643,9 +1653,17 @@ hipError_t launch_smr_ghost(const DevProblem* p, int stage, int ng, int nvirt, c
   return hipGetLastError();
 }
 
-hipError_t launch_smr_flux(int recon, int prec, const DevProblem* p, int stage, int parity, int last,
-                           int ncf, const int32_t block[3], hipStream_t s) {
-  using K = void (*)(const DevProblem*, int, int, int, int);
+hipError_t launch_smr_dt(const DevProblem* p, int nleaf, const int32_t block[3], int slot,
+                         hipStream_t s) {
+  const int cells = block[0] * block[1] * block[2];
+  const int gx = std::max(1, std::min((cells + 255) / 256, 64));
+  hipLaunchKernelGGL(k_smr_dt, dim3(gx, nleaf), dim3(256), 0, s, p, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_smr_flux(int recon, int prec, const DevProblem* p, int stage, int parity, int ncf,
+                           const int32_t block[3], hipStream_t s) {
+  using K = void (*)(const DevProblem*, int, int, int);
   static const K tab[4][2] = {{k_smr_flux<0, double>, k_smr_flux<0, float>},
                               {k_smr_flux<1, double>, k_smr_flux<1, float>},
                               {k_smr_flux<2, double>, k_smr_flux<2, float>},
@@ -1654,19 +1672,12 @@ hipError_t launch_smr_flux(int recon, int prec, const DevProblem* p, int stage, 
   const int area = std::max(block[1] * block[2], std::max(block[0] * block[2], block[0] * block[1]));
   const int gx = std::max(1, std::min((area + 255) / 256, 1024));
   for (int dir = 0; dir < 3; ++dir) {
-    hipLaunchKernelGGL(tab[recon][prec], dim3(gx, ncf), dim3(256), 0, s, p, stage, parity, dir, last);
+    hipLaunchKernelGGL(tab[recon][prec], dim3(gx, ncf), dim3(256), 0, s, p, stage, parity, dir);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-hipError_t launch_smr_dt(const DevProblem* p, int64_t ncell, int slot, hipStream_t s) {
-  int64_t g = (ncell + 255) / 256;
-  if (g > 4096) g = 4096;
-  if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_smr_dt, dim3((unsigned)g), dim3(256), 0, s, p, slot);
-  return hipGetLastError();
-}
 
 }  // namespace hy

@@ -19,7 +19,8 @@ hipError_t launch_scatter(const DevProblem* p, const double* src, double* dst, i
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_smr_ghost(const DevProblem* p, int stage, int ng, int nvirt, const int32_t block[3],
                             hipStream_t s);
-hipError_t launch_smr_flux(int recon, int prec, const DevProblem* p, int stage, int parity, int last,
-                           int ncf, const int32_t block[3], hipStream_t s);
-hipError_t launch_smr_dt(const DevProblem* p, int64_t ncell, int slot, hipStream_t s);
+hipError_t launch_smr_flux(int recon, int prec, const DevProblem* p, int stage, int parity, int ncf,
+                           const int32_t block[3], hipStream_t s);
+hipError_t launch_smr_dt(const DevProblem* p, int nleaf, const int32_t block[3], int slot,
+                         hipStream_t s);
 }  // namespace hy

@@ -475,6 +475,36 @@ def workload_kh_512(precision=FP64, N=512, block=128):
     return pb.with_(block=(block,) * 3, recon=PPM4, precision=precision), 10
 
 
+def inject_to_leaves(pb, box, leaves):
+    """Refined version of a uniform problem: coarse leaves keep their blocks;
+    each fine leaf repeats its parent's cells 2 x 2 x 2 (a piecewise-constant
+    fine state with the same cell averages), built leaf by leaf."""
+    bx, by, bz = (int(b) for b in pb.block)
+    lv = np.asarray(leaves).reshape(-1, 4)
+    out = np.empty((len(lv), 5, bz, by, bx), dtype=np.float64)
+    for q, (L, lx, ly, lz) in enumerate(lv):
+        if L == 0:
+            out[q] = pb.U[:, lz * bz:(lz + 1) * bz, ly * by:(ly + 1) * by, lx * bx:(lx + 1) * bx]
+            continue
+        x0, y0, z0 = lx * bx // 2, ly * by // 2, lz * bz // 2
+        par = pb.U[:, z0:z0 + bz // 2, y0:y0 + by // 2, x0:x0 + bx // 2]
+        out[q] = par.repeat(2, axis=1).repeat(2, axis=2).repeat(2, axis=3)
+    return pb.with_(U=out, refine=(tuple(box[0]), tuple(box[1])),
+                    name=(pb.name + " refined").strip())
+
+
+REFINED_BOX_256 = ((1, 1, 1), (3, 3, 3))
+
+
+def workload_turbulence_refined(leaves, precision=FP64, N=256, block=64, box=REFINED_BOX_256):
+    """The 256^3 turbulence workload with its central 2 x 2 x 2 root blocks
+    refined once: 56 MeshBlocks of 64^3 on level 0 and 64 on level 1 (31.5 M
+    cells), PLM, 20 steps; fine leaves start from their parents' cells.
+    ``leaves`` is the solver's leaf order for this mesh."""
+    pb, steps = workload_turbulence_256(precision=precision, N=N, block=block)
+    return inject_to_leaves(pb, box, leaves), steps
+
+
 SEDOV_SIZES = (32, 48, 64, 96, 128)
 
 

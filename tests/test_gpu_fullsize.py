@@ -9,6 +9,9 @@ times (chosen by the same whole-step autotuning on a scratch copy).
   this size take minutes of host time), and over the full 10 steps the
   properties that hold at any size: conservation to roundoff on the periodic
   grid, no floor firings, and FP64 vs mixed agreement within the mixed gate.
+* The refined 256^3 mesh of the benchmark (central 2^3 root blocks refined
+  once): one step against the reference solver, 20 steps for the same
+  properties.
 """
 import numpy as np
 import pytest
@@ -78,3 +81,30 @@ def test_kh_512_full_size(hy):
     r = _rel(Um, U)
     print(f"[kh512 {steps} steps] mixed vs FP64 rel L1 {r:.3e}", flush=True)
     assert r <= 1e-5
+
+
+def test_turbulence_256_refined_full_size(hy):
+    # the refined benchmark mesh (central 2^3 root blocks on level 1, 120
+    # leaves of 64^3): one whole step (both stages and the time step) against
+    # the reference solver (about 10 s of host time per step at this size),
+    # 20 steps for conservation, floors and FP64 vs mixed agreement
+    base, steps = P.workload_turbulence_256()
+    pb, _ = P.workload_turbulence_refined(hy.leaves(base.with_(refine=P.REFINED_BOX_256)))
+    lv = hy.leaves(pb)
+    U2, q2, launch = _run_tuned(hy, pb, 1)
+    ref = oracle.advance(pb, 1)
+    r = _rel(U2, ref["U"])
+    print(f"[refined 256 full] launch {launch} rel L1 after 1 step {r:.3e}", flush=True)
+    assert r <= 1e-12
+    assert abs(q2["dt"] / ref["dt"] - 1) <= 1e-11
+    U, q, _ = _run_tuned(hy, pb, steps)
+    vol = np.prod(pb.dx) * np.where(lv[:, 0] == 0, 1.0, 0.125)
+    s0 = np.einsum("q,qv->v", vol, pb.U.reshape(len(lv), 5, -1).sum(-1))
+    s1 = np.einsum("q,qv->v", vol, U.reshape(len(lv), 5, -1).sum(-1))
+    a = np.einsum("q,qv->v", vol, np.abs(U).reshape(len(lv), 5, -1).sum(-1))
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * a), (s1 - s0) / a
+    assert q["floor_hits"] == 0
+    Um, _, _ = _run_tuned(hy, pb.with_(precision=P.MIXED), steps)
+    rm = _rel(Um, U)
+    print(f"[refined 256 full] 20 steps: mixed vs FP64 rel L1 {rm:.3e}", flush=True)
+    assert rm <= 1e-5
