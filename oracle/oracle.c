@@ -666,6 +666,19 @@ static rk_coef rk_stage(int rk, int stage) {
   return k;
 }
 
+/* SSPRK(10,4) of Ketcheson (2008) in its two-register low-storage form:
+ * nine stages q1 <- q1 + h/6 L(q1); after the fifth, q2 <- q2/25 + 9 q1/25
+ * and q1 <- 15 q2 - 5 q1; the tenth u <- q2 + 3/5 q1 + h/10 L(q1). */
+static const rk_coef RK4_STAGE = {0.0, 1.0, 1.0 / 6.0};
+static const rk_coef RK4_LAST = {1.0, 3.0 / 5.0, 1.0 / 10.0};
+
+static void rk4_mix(double* Q2, double* q1, size_t nt) {
+  for (size_t c = 0; c < nt; ++c) {
+    Q2[c] = Q2[c] / 25.0 + 9.0 / 25.0 * q1[c];
+    q1[c] = 15.0 * Q2[c] - 5.0 * q1[c];
+  }
+}
+
 static void stage_formula(const or_params* p, const work* w, rk_coef k, const double* U0,
                           const double* Ust, double h, double* Uout) {
   const size_t nt = 5 * ncell(p);
@@ -768,26 +781,17 @@ int or_advance(const or_params* p, double* U, int nsteps, double* t, double* dt,
     const double h = *dt;
     const double* st = U;  /* state the stage differentiates */
     if (p->rk == 4) {
-      /* SSPRK(10,4) of Ketcheson (2008) in its low-storage form: nine stages
-       * q1 <- q1 + h/6 L(q1) with, after the fifth, q2 <- q2/25 + 9 q1/25 and
-       * q1 <- 15 q2 - 5 q1; then u <- q2 + 3/5 q1 + h/10 L(q1). q1 alternates
-       * between U1 and U2 so that no stage overwrites its own input. */
+      /* SSPRK(10,4) (RK4_STAGE, RK4_LAST, rk4_mix); q1 alternates between U1
+       * and U2 so that no stage overwrites its own input. */
       memcpy(Q2, U, nt * sizeof(double));
-      const rk_coef k16 = {0.0, 1.0, 1.0 / 6.0}, kend = {1.0, 3.0 / 5.0, 1.0 / 10.0};
       for (int stage = 1; stage <= 10; ++stage) {
         int bad = 0;
         hits += divergence(p, &w, st, &bad);
         if (bad) status = OR_ERR_STATE;
         double* out = (stage & 1) ? U1 : U2;
-        fofc += stage_apply(p, &w, stage < 10 ? k16 : kend, Q2, st, h, out);
+        fofc += stage_apply(p, &w, stage < 10 ? RK4_STAGE : RK4_LAST, Q2, st, h, out);
         st = out;
-        if (stage == 5) {
-          double* q1 = out;
-          for (size_t c = 0; c < nt; ++c) {
-            Q2[c] = Q2[c] / 25.0 + 9.0 / 25.0 * q1[c];
-            q1[c] = 15.0 * Q2[c] - 5.0 * q1[c];
-          }
-        }
+        if (stage == 5) rk4_mix(Q2, out, nt);
       }
     } else {
       for (int stage = 1; stage <= p->rk; ++stage) {
@@ -1202,13 +1206,8 @@ int or_smr_advance(const or_params* p, const or_smr* s, double* U, int nsteps, d
       if (bad) status = OR_ERR_STATE;
       double* out = (stage & 1) ? U1 : U2;
       if (p->rk == 4) {
-        const rk_coef k16 = {0.0, 1.0, 1.0 / 6.0}, kend = {1.0, 3.0 / 5.0, 1.0 / 10.0};
-        smr_stage(&m, w, stage < 10 ? k16 : kend, Q2, S, h, out);
-        if (stage == 5)
-          for (size_t c = 0; c < nt; ++c) {
-            Q2[c] = Q2[c] / 25.0 + 9.0 / 25.0 * out[c];
-            out[c] = 15.0 * Q2[c] - 5.0 * out[c];
-          }
+        smr_stage(&m, w, stage < 10 ? RK4_STAGE : RK4_LAST, Q2, S, h, out);
+        if (stage == 5) rk4_mix(Q2, out, nt);
       } else {
         smr_stage(&m, w, rk_stage(p->rk, stage), U, S, h, out);
       }

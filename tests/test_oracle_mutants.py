@@ -53,7 +53,7 @@ MUTANTS = [
     ("ppmx_overshoot_factor", "aR = a + 2.0 * dm;", "aR = a + 3.0 * dm;"),
     ("ppmx_limiter_constant", "#define OR_PPMX_C 1.25", "#define OR_PPMX_C 0.75"),
     ("rk4_combine_weight", "Q2[c] = Q2[c] / 25.0 + 9.0 / 25.0 * q1[c];", "Q2[c] = Q2[c] / 25.0 + 9.0 / 24.0 * q1[c];"),
-    ("rk4_last_step", "kend = {1.0, 3.0 / 5.0, 1.0 / 10.0}", "kend = {1.0, 3.0 / 5.0, 1.0 / 6.0}"),
+    ("rk4_last_step", "RK4_LAST = {1.0, 3.0 / 5.0, 1.0 / 10.0}", "RK4_LAST = {1.0, 3.0 / 5.0, 1.0 / 6.0}"),
     ("ghost_periodic_offset", "return bchi == OR_PERIODIC ? c % n : n - 1;",
      "return bchi == OR_PERIODIC ? (c + 1) % n : n - 1;"),
     ("ghost_outflow_index", "return bclo == OR_PERIODIC ? ((c % n) + n) % n : 0;",
