@@ -1361,6 +1361,8 @@ __global__ void __launch_bounds__(256) k_smr_ghost(const DevProblem* __restrict_
   }
 }
 
+constexpr int kSmrCells = 51;  // face cells per k_smr_flux workgroup pass (5 threads each)
+
 // Flux correction along direction `dir` (Sec. 2: the flux through a coarse
 // face shared with finer blocks is the finer blocks' flux): for each coarse
 // face next to 4 fine faces (cfinfo), the coarse cell adds
@@ -1388,47 +1390,60 @@ __global__ void __launch_bounds__(256) k_smr_flux(const DevProblem* __restrict__
   const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
   const int32_t* bq = P.binfo + (int64_t)q * kLeafInts;
   const int n1 = 2 * P.nroot[d] * bd[d];
-  Geo gc;
-  geo_init(gc, P, q);
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < bd[t1] * bd[t2]; c += gridDim.x * blockDim.x) {
-    const int a2 = c / bd[t1], a1 = c - a2 * bd[t1];
-    int cf[3];
-    cf[d] = side ? bd[d] : 0;  // face_pair's cell index: the face's upper cell
-    cf[t1] = a1;
-    cf[t2] = a2;
-    T fc[5], unused[5];
-    face_pair<RECON, T>(gc, fl, gas, S, d, cf[0], cf[1], cf[2], fc, unused);
-    double ff[4][5];
-#pragma unroll 1
-    for (int h = 0; h < 4; ++h) {
-      int g3[3];
-      g3[d] = side ? 2 * (bq[7 + d] + 1) * bd[d] : 2 * bq[7 + d] * bd[d] - 1;
-      g3[d] = (g3[d] + n1) % n1;
-      g3[t1] = 2 * (bq[7 + t1] * bd[t1] + a1) + (h & 1);
-      g3[t2] = 2 * (bq[7 + t2] * bd[t2] + a2) + (h >> 1);
-      const int lx = g3[0] / bd[0], ly = g3[1] / bd[1], lz = g3[2] / bd[2];
-      const int r = (lx >> 1) + P.nroot[0] * ((ly >> 1) + P.nroot[1] * (lz >> 1));
-      const int qf = P.rinfo[2 * r + 1] + (lx & 1) + 2 * (ly & 1) + 4 * (lz & 1);
-      int lf[3] = {g3[0] - lx * bd[0], g3[1] - ly * bd[1], g3[2] - lz * bd[2]};
-      lf[d] = side ? 0 : bd[d];
-      Geo gf;
-      geo_init(gf, P, qf);
-      T fo[5];
-      face_pair<RECON, T>(gf, fl, gas, S, d, lf[0], lf[1], lf[2], fo, unused);
+  // five threads per face cell: h = 0 the coarse flux, h = 1..4 the fine
+  // ones (more threads in flight than one thread doing all five)
+  __shared__ double sFl[kSmrCells][5][5];
+  const int cs = threadIdx.x / 5, h = threadIdx.x - 5 * cs;
+  const int area = bd[t1] * bd[t2];
+  for (int base = blockIdx.x * kSmrCells; base < area; base += gridDim.x * kSmrCells) {
+    const int c = base + cs;
+    const bool valid = cs < kSmrCells && c < area;
+    const int a2 = valid ? c / bd[t1] : 0, a1 = valid ? c - a2 * bd[t1] : 0;
+    if (valid) {
+      Geo g;
+      int lf[3];
+      if (h == 0) {
+        geo_init(g, P, q);
+        lf[d] = side ? bd[d] : 0;  // face_pair's cell index: the face's upper cell
+        lf[t1] = a1;
+        lf[t2] = a2;
+      } else {
+        const int k4 = h - 1;
+        int g3[3];
+        g3[d] = side ? 2 * (bq[7 + d] + 1) * bd[d] : 2 * bq[7 + d] * bd[d] - 1;
+        g3[d] = (g3[d] + n1) % n1;
+        g3[t1] = 2 * (bq[7 + t1] * bd[t1] + a1) + (k4 & 1);
+        g3[t2] = 2 * (bq[7 + t2] * bd[t2] + a2) + (k4 >> 1);
+        const int lx = g3[0] / bd[0], ly = g3[1] / bd[1], lz = g3[2] / bd[2];
+        const int r = (lx >> 1) + P.nroot[0] * ((ly >> 1) + P.nroot[1] * (lz >> 1));
+        const int qf = P.rinfo[2 * r + 1] + (lx & 1) + 2 * (ly & 1) + 4 * (lz & 1);
+        lf[0] = g3[0] - lx * bd[0];
+        lf[1] = g3[1] - ly * bd[1];
+        lf[2] = g3[2] - lz * bd[2];
+        lf[d] = side ? 0 : bd[d];
+        geo_init(g, P, qf);
+      }
+      T fo[5], unused[5];
+      face_pair<RECON, T>(g, fl, gas, S, d, lf[0], lf[1], lf[2], fo, unused);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) ff[h][v] = (double)fo[v];
+      for (int v = 0; v < 5; ++v) sFl[cs][h][v] = (double)fo[v];
     }
-    int cc[3];
-    cc[d] = side ? bd[d] - 1 : 0;
-    cc[t1] = a1;
-    cc[t2] = a2;
-    const int64_t off = (int64_t)q * P.bstride + ((int64_t)cc[2] * P.by + cc[1]) * P.bx + cc[0];
+    __syncthreads();
+    if (valid && h == 0) {
+      int cc[3];
+      cc[d] = side ? bd[d] - 1 : 0;
+      cc[t1] = a1;
+      cc[t2] = a2;
+      const int64_t off = (int64_t)q * P.bstride + ((int64_t)cc[2] * P.by + cc[1]) * P.bx + cc[0];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const double mean = ((ff[0][v] + ff[1][v]) + (ff[2][v] + ff[3][v])) * 0.25;
-      const double dl = side ? ((double)fc[v] - mean) * idc : (mean - (double)fc[v]) * idc;
-      Out[off + v * P.vstride] += cst * dl;
+      for (int v = 0; v < 5; ++v) {
+        const double fc = sFl[cs][0][v];
+        const double mean = ((sFl[cs][1][v] + sFl[cs][2][v]) + (sFl[cs][3][v] + sFl[cs][4][v])) * 0.25;
+        const double dl = side ? (fc - mean) * idc : (mean - fc) * idc;
+        Out[off + v * P.vstride] += cst * dl;
+      }
     }
+    __syncthreads();  // sFl is reused by the next group
   }
 }
 
@@ -1670,7 +1685,7 @@ hipError_t launch_smr_flux(int recon, int prec, const DevProblem* p, int stage, 
                               {k_smr_flux<3, double>, k_smr_flux<3, float>}};
   if (recon < 0 || recon > 3 || prec < 0 || prec > 1) return hipErrorInvalidValue;
   const int area = std::max(block[1] * block[2], std::max(block[0] * block[2], block[0] * block[1]));
-  const int gx = std::max(1, std::min((area + 255) / 256, 1024));
+  const int gx = std::max(1, std::min((area + kSmrCells - 1) / kSmrCells, 1024));
   for (int dir = 0; dir < 3; ++dir) {
     hipLaunchKernelGGL(tab[recon][prec], dim3(gx, ncf), dim3(256), 0, s, p, stage, parity, dir);
     const hipError_t e = hipGetLastError();
