@@ -1298,37 +1298,11 @@ __device__ __forceinline__ double minmod2(double a, double b) {
   return fabs(a) < fabs(b) ? a : b;
 }
 
-__device__ void smr_level1(const DevProblem& P, const double* S, int i, int j, int k, double u[5]) {
-  const int r = i / (2 * P.bx) + P.nroot[0] * (j / (2 * P.by) + P.nroot[1] * (k / (2 * P.bz)));
-  if (P.rinfo[2 * r]) {
-    smr_fine5(P, S, i, j, k, u);
-    return;
-  }
-  const int c[3] = {i >> 1, j >> 1, k >> 1};
-  const int odd[3] = {i & 1, j & 1, k & 1};
-  const int n0[3] = {P.nroot[0] * P.bx, P.nroot[1] * P.by, P.nroot[2] * P.bz};
-  double C[5], t[3][5];
-  smr_level0(P, S, c[0], c[1], c[2], C);
-  for (int d = 0; d < 3; ++d) {
-    int lo[3] = {c[0], c[1], c[2]}, hi[3] = {c[0], c[1], c[2]};
-    lo[d] = wrap_or_clamp(c[d] - 1, n0[d], P.periodic[d]);
-    hi[d] = wrap_or_clamp(c[d] + 1, n0[d], P.periodic[d]);
-    double a[5], b[5];
-    smr_level0(P, S, lo[0], lo[1], lo[2], a);
-    smr_level0(P, S, hi[0], hi[1], hi[2], b);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const double sl = minmod2(C[v] - a[v], b[v] - C[v]);
-      t[d][v] = odd[d] ? sl : -sl;
-    }
-  }
-#pragma unroll
-  for (int v = 0; v < 5; ++v) u[v] = C[v] + 0.25 * ((t[0][v] + t[1][v]) + t[2][v]);
-}
+constexpr int kGhostCC = 32;  // coarse cells per k_smr_ghost prolongation pass (256 threads)
 
-// Fill every ghost slab of one problem from the stage's source register, one
-// thread per slab cell (all 5 variables). Slab blocks follow the leaves in the
-// same register; the slab cell sits where ghost_local looks for it (the
+// Fill every ghost slab of one problem (grid row = slab) from the stage's
+// source register, all 5 variables per cell. Slab blocks follow the leaves in
+// the same register; a slab cell sits where ghost_local looks for it (the
 // neighbour block's frame), so the stage kernel reads it unchanged.
 __global__ void __launch_bounds__(256) k_smr_ghost(const DevProblem* __restrict__ Pp, int stage, int ng) {
   const DevProblem& P = *Pp;
@@ -1340,24 +1314,95 @@ __global__ void __launch_bounds__(256) k_smr_ghost(const DevProblem* __restrict_
   const int lev = b[0];
   const int bd[3] = {P.bx, P.by, P.bz};
   const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-  const int area = bd[t1] * bd[t2];
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ng * area; c += gridDim.x * blockDim.x) {
-    const int l = c / area, rem = c - l * area;
-    const int a2 = rem / bd[t1], a1 = rem - a2 * bd[t1];
-    int g3[3], s3[3];
-    g3[t1] = b[7 + t1] * bd[t1] + a1;
-    g3[t2] = b[7 + t2] * bd[t2] + a2;
-    const int nl = (P.nroot[d] * bd[d]) << lev;
-    g3[d] = wrap_or_clamp(side ? b[7 + d] * bd[d] + bd[d] + l : b[7 + d] * bd[d] - 1 - l, nl, P.periodic[d]);
-    double u[5];
-    if (lev == 0) smr_level0(P, S, g3[0], g3[1], g3[2], u);
-    else smr_level1(P, S, g3[0], g3[1], g3[2], u);
-    s3[t1] = a1;
-    s3[t2] = a2;
-    s3[d] = side ? l : bd[d] - 1 - l;
-    double* o = S + (int64_t)(P.nblocks + vb) * P.bstride + ((int64_t)s3[2] * P.by + s3[1]) * P.bx + s3[0];
+  const int nl = (P.nroot[d] * bd[d]) << lev;
+  double* slab = S + (int64_t)(P.nblocks + vb) * P.bstride;
+  auto ghost_d = [&](int l) {  // global index along d of ghost layer l, at the slab's level
+    return wrap_or_clamp(side ? b[7 + d] * bd[d] + bd[d] + l : b[7 + d] * bd[d] - 1 - l, nl, P.periodic[d]);
+  };
+  if (lev == 0) {  // coarse slab next to a refined root: restriction, one thread per ghost cell
+    const int area = bd[t1] * bd[t2];
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ng * area; c += gridDim.x * blockDim.x) {
+      const int l = c / area, rem = c - l * area;
+      const int a2 = rem / bd[t1], a1 = rem - a2 * bd[t1];
+      int g3[3], s3[3];
+      g3[t1] = b[7 + t1] * bd[t1] + a1;
+      g3[t2] = b[7 + t2] * bd[t2] + a2;
+      g3[d] = ghost_d(l);
+      double u[5];
+      smr_level0(P, S, g3[0], g3[1], g3[2], u);
+      s3[t1] = a1;
+      s3[t2] = a2;
+      s3[d] = side ? l : bd[d] - 1 - l;
+      double* o = slab + ((int64_t)s3[2] * P.by + s3[1]) * P.bx + s3[0];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) o[v * P.vstride] = u[v];
+      for (int v = 0; v < 5; ++v) o[v * P.vstride] = u[v];
+    }
+    return;
+  }
+  // fine slab next to an unrefined root: prolongation. Per pass, kGhostCC
+  // coarse cells under the slab: 7 threads per coarse cell fetch its level-0
+  // value and its 6 neighbours' into LDS, then 8 threads per coarse cell form
+  // its children that lie in the slab (each child with the arithmetic of R30).
+  __shared__ double sv[kGhostCC][7][5];
+  const int h1 = bd[t1] / 2, h2 = bd[t2] / 2;
+  const int ncc = ((ng + 1) / 2) * h1 * h2;
+  const int n0[3] = {P.nroot[0] * P.bx, P.nroot[1] * P.by, P.nroot[2] * P.bz};
+  auto coarse_of = [&](int cidx, int c3[3], int& L, int& c1, int& c2) {
+    L = cidx / (h1 * h2);
+    const int rem = cidx - L * (h1 * h2);
+    c2 = rem / h1;
+    c1 = rem - c2 * h1;
+    c3[t1] = (b[7 + t1] * bd[t1] >> 1) + c1;
+    c3[t2] = (b[7 + t2] * bd[t2] >> 1) + c2;
+    c3[d] = ghost_d(2 * L) >> 1;
+  };
+  for (int base = blockIdx.x * kGhostCC; base < ncc; base += gridDim.x * kGhostCC) {
+    {
+      const int cs = threadIdx.x / 7, kk = threadIdx.x - 7 * cs;  // kk 0: the cell; 1 + 2a + up: neighbours
+      if (cs < kGhostCC && base + cs < ncc) {
+        int c3[3], L, c1, c2;
+        coarse_of(base + cs, c3, L, c1, c2);
+        if (kk > 0) {
+          const int a = (kk - 1) >> 1, up = (kk - 1) & 1;
+          c3[a] = wrap_or_clamp(c3[a] + (up ? 1 : -1), n0[a], P.periodic[a]);
+        }
+        double u[5];
+        smr_level0(P, S, c3[0], c3[1], c3[2], u);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sv[cs][kk][v] = u[v];
+      }
+    }
+    __syncthreads();
+    {
+      const int cs = threadIdx.x >> 3, e = threadIdx.x & 7;
+      if (cs < kGhostCC && base + cs < ncc) {
+        int c3[3], L, c1, c2;
+        coarse_of(base + cs, c3, L, c1, c2);
+        const int l = 2 * L + (e & 1);
+        if (l < ng) {
+          int odd[3], s3[3];
+          odd[d] = ghost_d(l) & 1;
+          odd[t1] = (e >> 1) & 1;  // leaf bases are even: the local parity is the global one
+          odd[t2] = e >> 2;
+          s3[d] = side ? l : bd[d] - 1 - l;
+          s3[t1] = 2 * c1 + odd[t1];
+          s3[t2] = 2 * c2 + odd[t2];
+          double* o = slab + ((int64_t)s3[2] * P.by + s3[1]) * P.bx + s3[0];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            const double C = sv[cs][0][v];
+            double t[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              const double sl = minmod2(C - sv[cs][1 + 2 * a][v], sv[cs][2 + 2 * a][v] - C);
+              t[a] = odd[a] ? sl : -sl;
+            }
+            o[v * P.vstride] = C + 0.25 * ((t[0] + t[1]) + t[2]);
+          }
+        }
+      }
+    }
+    __syncthreads();  // sv is reused by the next pass
   }
 }
 
