@@ -76,6 +76,26 @@ def test_turbulence_refined_box(hy, recon, rk):
     _check(hy, pb, 6, f"turb smr {recon}/{rk}")
 
 
+def test_non_cubic_blocks_kh(hy):
+    # bx, by, bz all different: slab faces and flux faces of three different
+    # shapes, on both levels
+    make = lambda s: P.kelvin_helmholtz(n=(64 * s, 48 * s, 48 * s), seed=12, bg_noise=1e-6).with_(
+        block=(16, 12, 24), recon=P.PLM, rk=2)
+    pb = _refined(make, ((1, 1, 0), (3, 3, 1)))
+    _check(hy, pb, 5, "non-cubic smr kh")
+
+
+@pytest.mark.parametrize("recon,rk", [(P.PPMX, 3), (P.WENOZ, 4)])
+def test_non_cubic_blocks_turbulence(hy, recon, rk):
+    # PPMX runs on turbulence here: on the noisy KH layer, prolongation gives
+    # the 8 children of a noise-level extremum equal values, and PPMX's
+    # extremum switch then turns a one-ulp change of the data into 1e-10
+    # (pinned on the reference solver alone in test_oracle_smr.py)
+    make = lambda s: P.turbulence(N=48 * s, seed=12, kmax=6).with_(block=(16, 12, 24), recon=recon, rk=rk)
+    pb = _refined(make, ((1, 1, 0), (2, 3, 1)))
+    _check(hy, pb, 5, f"non-cubic smr {recon}/{rk}")
+
+
 def test_sod_crossing_refinement_outflow(hy):
     make = lambda s: P.sod(N=64 * s, axis=0, ntrans=8 * s, gamma=1.4).with_(block=(8, 8, 8))
     pb = _refined(make, ((4, 0, 0), (6, 1, 1)))

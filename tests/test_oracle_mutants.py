@@ -122,7 +122,8 @@ def _fast_pins(O):
     yield lambda: f2.test_time_order_of_the_integrators(O, P.WENOZ, 3, 256, (0.8, 0.4), 2.75, 3.3)
     yield lambda: f2.test_time_order_by_richardson(O, 4, 4.0)
     yield lambda: smr.test_face_ghosts_exact_for_linear_fields(O, P.PLM)
-    yield lambda: smr.test_face_ghosts_match_independent_restriction_and_prolongation(O)
+    yield lambda: smr.test_face_ghosts_match_independent_restriction_and_prolongation(
+        O, (32, 24, 24), (8, 6, 12), ((1, 1, 0), (3, 3, 1)))
     yield lambda: smr.test_uniform_state_stays_uniform_bitwise(O, P.PERIODIC, P.PLM)
     yield lambda: smr.test_periodic_refined_mesh_conserves(O, P.PLM, 2)
     yield lambda: smr.test_full_refinement_equals_uniform_fine_grid_bitwise(O, P.PERIODIC)

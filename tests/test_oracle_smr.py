@@ -150,27 +150,29 @@ def _rep_numpy(pb, lv, U):
     return R0, R1
 
 
-def test_face_ghosts_match_independent_restriction_and_prolongation(oracle_lib):
-    pb = P.uniform(n=(32, 16, 24), rho=1.0, v=(0, 0, 0), p=1.0, bc=P.PERIODIC)
-    pb = pb.with_(block=(8, 8, 8), recon=P.PPM4, refine=((0, 0, 1), (2, 1, 2)))
+@pytest.mark.parametrize("n,block,box", [((32, 16, 24), (8, 8, 8), ((0, 0, 1), (2, 1, 2))),
+                                         ((32, 24, 24), (8, 6, 12), ((1, 1, 0), (3, 3, 1)))])
+def test_face_ghosts_match_independent_restriction_and_prolongation(oracle_lib, n, block, box):
+    pb = P.uniform(n=n, rho=1.0, v=(0, 0, 0), p=1.0, bc=P.PERIODIC)
+    pb = pb.with_(block=block, recon=P.PPM4, refine=box)
     lv = oracle_lib.smr_leaves(pb)
+    bx, by, bz = block
     rng = np.random.default_rng(11)
-    U = rng.uniform(0.5, 2.0, size=(len(lv), 5, 8, 8, 8))
+    U = rng.uniform(0.5, 2.0, size=(len(lv), 5, bz, by, bx))
     G = oracle_lib.smr_fill_ghosts(pb.with_(U=U))
     R0, R1 = _rep_numpy(pb, lv, U)
     g = 3
     for q, (L, lx, ly, lz) in enumerate(lv):
         R = R1 if L else R0
         N = R.shape[1:][::-1]
-        base = (lx * 8, ly * 8, lz * 8)
-        ii = [np.arange(base[e] - g, base[e] + 8 + g) % N[e] for e in range(3)]
+        base = (lx * bx, ly * by, lz * bz)
+        ii = [np.arange(base[e] - g, base[e] + block[e] + g) % N[e] for e in range(3)]
         full = R[:, ii[2]][:, :, ii[1]][:, :, :, ii[0]]
-        mask = np.zeros((8 + 2 * g,) * 3, dtype=bool)  # face ghosts only
-        inner = slice(g, g + 8)
+        mask = np.zeros((bz + 2 * g, by + 2 * g, bx + 2 * g), dtype=bool)  # face ghosts only
         for d in range(3):
-            m = [inner, inner, inner]
-            m[2 - d] = np.r_[0:g, 8 + g:8 + 2 * g]
-            mask[np.ix_(*[np.arange(8 + 2 * g)[s] for s in m])] = True
+            m = [np.arange(g, g + block[e]) for e in (2, 1, 0)]
+            m[2 - d] = np.r_[0:g, block[d] + g:block[d] + 2 * g]
+            mask[np.ix_(*m)] = True
         np.testing.assert_allclose(G[q][:, mask], full[:, mask], rtol=2e-15, atol=0)
 
 
@@ -326,3 +328,26 @@ def test_sod_shock_crosses_refinement(oracle_lib):
     assert sel.sum() >= 3
     assert np.all(np.abs(rho[sel] / rho_sr - 1) < 0.02), rho[sel]
     assert xsh > 0.875  # the shock has left the fine region again
+
+
+def test_ppmx_on_prolongated_plateaus_is_ill_conditioned(oracle_lib):
+    # Minmod prolongation gives the 8 children of a coarse extremum the same
+    # value; on the noisy KH layer (noise-level extrema everywhere) these exact
+    # plateaus sit in the fine ghosts, where PPMX's extremum switch is
+    # discontinuous: a one-ulp change of half the initial values moves the
+    # result by ~1e-10, while PLM (and PPMX without refinement) move by
+    # rounding only. Two correct implementations can therefore differ there
+    # beyond the FP64 parity gate; the GPU parity cases for PPMX use smooth data.
+    def sensitivity(recon, refine):
+        make = lambda s: P.kelvin_helmholtz(n=(64 * s, 48 * s, 48 * s), seed=12, bg_noise=1e-6).with_(
+            block=(16, 12, 24), recon=recon, rk=3)
+        pb = _refined(oracle_lib, make, ((1, 1, 0), (3, 3, 1))) if refine else make(1)
+        r0 = oracle_lib.advance(pb, 5)
+        U1 = pb.U.copy()
+        mask = np.random.default_rng(1).random(U1.shape) < 0.5
+        U1[mask] = np.nextafter(U1[mask], np.inf)
+        r1 = oracle_lib.advance(pb, 5, U=U1)
+        return float(np.abs(r1["U"] - r0["U"]).sum() / np.abs(r0["U"]).sum())
+    assert sensitivity(P.PPMX, True) > 1e-12
+    assert sensitivity(P.PLM, True) < 1e-14
+    assert sensitivity(P.PPMX, False) < 1e-14
