@@ -7,7 +7,8 @@
  * 2024, arXiv:2409.16053: Sec. 3, Eq. 1; Sec. 3.1, Eq. 4). The mesh is a
  * uniform Cartesian grid (Sec. 2, "Cartesian coordinates only") cut into
  * equal MeshBlocks that are processed together as one MeshBlockPack
- * (Sec. 2, "MeshBlockPacks"; "Data locality"). Each step runs the paper's
+ * (Sec. 2, "MeshBlockPacks"; "Data locality"), optionally with a box of
+ * MeshBlocks refined once (static mesh refinement, hy_config.refine_*). Each step runs the paper's
  * reconstruct-solve-advance sequence (Sec. 3): ghost zones (Sec. 2,
  * "Boundary conditions"), cons-to-prim, PLM, PPM4, PPMX or WENO-Z
  * reconstruction on primitives, HLLC fluxes in x, y and z, flux divergence
