@@ -14,7 +14,7 @@
  *   -> reconstruction on primitives, PLM, PPM4, PPMX or WENO-Z (Sec. 3)
  *   -> HLLC Riemann fluxes in x, y and z (Sec. 3; Toro's textbook, Ch. 10)
  *   -> flux divergence and a low-storage SSP-RK stage (Sec. 3, method of lines;
- *      one, two or three stages)
+ *      RK1, RK2, RK3 or the ten-stage fourth-order RK4)
  *   -> optionally, first-order flux correction with LLF fluxes (Sec. 3, FOFC)
  *   -> CFL time step, Eq. 3: CFL times the minimum over all cells and all
  *      dimensions of dx_d / lambda_max,d.

@@ -1,11 +1,12 @@
 // hy_internal.h -- types shared by the host runtime and the gfx950 kernels.
 //
-// A problem's device workspace starts with a 512-byte header: the descriptor
+// A problem's device workspace starts with a 1024-byte header: the descriptor
 // below (read by every workgroup with scalar loads) and its counters. Two FP64
-// state registers follow (three for RK3), each a MeshBlockPack laid out as
-// [block m][variable v][k][j][i] with i (x) fastest and no ghost cells:
+// state registers follow (three for RK3 and RK4), each a MeshBlockPack laid
+// out as [block m][variable v][k][j][i] with i (x) fastest and no ghost cells:
 // ghost zones are filled into each tile's LDS halo directly from the
-// neighbouring block's interior or from the physical boundary condition.
+// neighbouring block's interior or from the physical boundary condition (on a
+// refined mesh, from a ghost slab where the neighbour is on the other level).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
