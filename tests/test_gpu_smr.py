@@ -226,7 +226,8 @@ def test_random_refined_configurations(hy, seed):
     rng = np.random.default_rng(1000 + seed)
     recon = int(rng.choice([P.PLM, P.PPM4, P.WENOZ, P.PPMX]))
     rk = int(rng.integers(1, 5))
-    prec = int(rng.choice([P.FP64, P.MIXED]))
+    int(rng.choice([P.FP64, P.MIXED]))  # (kept so that the later draws stay put)
+    prec = P.FP64 if seed % 2 == 0 else P.MIXED
     nr = rng.integers(2, 4, size=3)
     block = tuple(int(b) for b in rng.choice([8, 12, 16], size=3))
     n = tuple(int(nr[d] * block[d]) for d in range(3))
@@ -235,7 +236,7 @@ def test_random_refined_configurations(hy, seed):
     bc = tuple((b, b) for b in rng.choice([P.PERIODIC, P.OUTFLOW], size=3))
     make = lambda s: _smooth([n[d] * s for d in range(3)], bc, seed, block, recon=recon, rk=rk)
     pb = _refined(make, (lo, hi))
-    label = f"random smr {seed}: n={n} block={block} box={lo}-{hi} bc={[b[0] for b in bc]} prec={prec}"
+    label = f"random smr {seed}: n={n} block={block} box={lo}-{hi} bc={[int(b[0]) for b in bc]} prec={prec}"
     if prec == P.FP64:
         _check(hy, pb, 4, label)
     else:
