@@ -245,3 +245,22 @@ def test_workspace_has_third_register(hy):
     for bad in (-1, 5):
         with pytest.raises(hy.HydroError):
             hy.workspace_bytes(pb.with_(rk=bad))
+
+
+@pytest.mark.parametrize("rk", [1, 4])
+def test_state_reload_between_advances(hy, rk):
+    # the time-step slot the next step reduces into must start cleared after
+    # hy_set_state at either step parity (RK1 has no earlier launch in its
+    # step to clear it); each segment is compared with the reference solver
+    pa = P.turbulence(N=32, seed=31, kmax=8).with_(block=(16, 16, 16), rk=rk)
+    pb = P.sedov(N=32, seed=32).with_(block=(16, 16, 16), rk=rk)
+    g = hy.Problem(pa).set_state()
+    for k, (pp, n) in enumerate(((pa, 3), (pb, 2), (pa, 1))):
+        if k:
+            g.set_state(pp.U)
+        g.advance(n)
+        U, q = g.get_state(), g.query()
+        ref = oracle.advance(pp, n)
+        assert _rel(U, ref["U"]) <= 1e-12
+        assert abs(q["dt"] / ref["dt"] - 1) <= 1e-11, (k, q["dt"], ref["dt"])
+    g.close()
