@@ -49,9 +49,12 @@ FP64_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 
 def kernel_source_hash():
     """Hash of the kernel sources with comments and blank lines removed (a
-    comment edit does not change the kernels the counters were taken on)."""
+    comment edit does not change the kernels the counters were taken on) and
+    of the compiler flags other than include paths."""
     import re
+    from paper_2409_16053_amd import build
     h = hashlib.sha256()
+    h.update(" ".join(f for f in build.CFLAGS if not f.startswith("-I")).encode())
     for f in ("hy_kernels.hip", "hy_internal.h"):
         with open(os.path.join(ROOT, "paper_2409_16053_amd", "csrc", f)) as fh:
             src = fh.read()

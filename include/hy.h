@@ -236,7 +236,7 @@ hy_status hy_get_launch(const hy_problem* p, int32_t* variant, int32_t* kc);
  * leave the state unchanged; with full_steps > 0 each timing runs that many
  * complete RK steps (FOFC and counters included), after one warm-up step,
  * which ADVANCES the state (tune a scratch copy). Synchronous. Returns the chosen
- * shape in *variant/*kc (either may be NULL) and its time per stage in
+ * shape in *variant and *kc (either may be NULL) and its time per stage in
  * *us_per_stage. */
 hy_status hy_autotune(hy_problem* p, void* hip_stream, int32_t full_steps, int32_t* variant,
                       int32_t* kc, double* us_per_stage);

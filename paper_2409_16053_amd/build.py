@@ -1,8 +1,10 @@
 """Build ``libhy.so`` (the gfx950 kernels and the C ABI of include/hy.h).
 
 Compiles every ``csrc/*.hip`` with hipcc for gfx950 into ``_build/`` and links
-them into ``paper_2409_16053_amd/libhy.so``. Flags: -O3, no floating-point
-contraction (every kernel instantiation then does identical per-cell
+them into ``paper_2409_16053_amd/libhy.so``. Flags: -O3, floating-point
+contraction within a source expression only (-ffp-contract=on: a * b + c
+written as one expression becomes an FMA, decided when the expression is
+compiled, so every kernel instantiation still does identical per-cell
 arithmetic), and packed-FP32 instructions disabled.
 """
 from __future__ import annotations
@@ -22,7 +24,7 @@ LIB = os.path.join(PKG, "libhy.so")
 ARCH = os.environ.get("HY_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
-CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
+CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=on",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", f"-I{INC}", f"-I{CSRC}"]
 

@@ -25,9 +25,10 @@
 //
 // Precision. T = double or float is the type of reconstruction and the
 // Riemann solve. Cons-to-prim, the flux divergence, the RK update and the time
-// step are always FP64. The library is built with -ffp-contract=off so every
-// instantiation performs identical per-cell arithmetic; FMAs are written out
-// where wanted.
+// step are always FP64. The library is built with -ffp-contract=on: a * b + c
+// within one source expression becomes an FMA, decided per expression when it
+// is compiled, so every instantiation still performs identical per-cell
+// arithmetic; the Newton steps of the reciprocals are written as FMAs.
 #include <algorithm>
 
 #include "hy_internal.h"
