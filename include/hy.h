@@ -255,6 +255,31 @@ hy_status hy_copy_probe(void* dst, const void* src, size_t bytes, void* hip_stre
 hy_status hy_advance_timed(hy_problem* p, int32_t nsteps, void* hip_stream, double* ms_stage1,
                            double* ms_stage2);
 
+/* ---------------- allocation-free entry point ------------------------------ */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc). Same update
+ * as hy_create + hy_set_state(HY_DEVICE) + hy_advance + hy_get_state(HY_DEVICE)
+ * with the workspace in a library-owned device array of HY_NOALLOC_MAX_BYTES
+ * per GPU (taken when the library is loaded, held until the process ends).
+ *  cfg     as for hy_create; refined meshes are not accepted.
+ *  U       device pointer, double[5][nz][ny][nx] (the hy_set_state layout):
+ *          read as the initial state, overwritten with the state after
+ *          nsteps steps.
+ *  t0      simulation time of the initial state.
+ *  out     NULL, or a device pointer to double[3] that receives the time
+ *          after the steps, the next time step and 1.0 if a non-finite state
+ *          or rho <= 0 was seen (else 0.0).
+ * Async on `hip_stream`; calls no hipMalloc/hipFree, no memset or host copy
+ * (graph-capturable). The launch shape is the one hy_create would pick.
+ * Errors: HY_ERR_ARG (bad config, NULL U, nsteps < 0, refinement),
+ * HY_ERR_NOMEM if hy_workspace_bytes(cfg) exceeds HY_NOALLOC_MAX_BYTES,
+ * HY_ERR_HIP. Every call on one GPU uses that GPU's single array, which keeps
+ * the last call's contents: calls that overlap on one GPU (other threads,
+ * other streams without ordering) race and must not be issued. */
+#define HY_NOALLOC_MAX_BYTES (256ull << 20)
+hy_status hy_advance_noalloc(const hy_config* cfg, double* U, int32_t nsteps, double t0, double* out,
+                             void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

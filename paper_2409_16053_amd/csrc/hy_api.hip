@@ -540,30 +540,18 @@ int32_t hy_leaves(const hy_config* cfg, int32_t* out) {
   return L.nleaf;
 }
 
-hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_problem** out) {
-  std::string msg;
-  if (!out) return fail(HY_ERR_ARG, "out is NULL");
-  *out = nullptr;
-  if (!validate(cfg, msg)) return fail(HY_ERR_ARG, msg);
-  if (!dev_ws) return fail(HY_ERR_ARG, "workspace is NULL");
-  if (((uintptr_t)dev_ws) & 255) return fail(HY_ERR_ARG, "workspace must be 256-byte aligned");
-  const size_t need = hy_workspace_bytes(cfg);
-  if (ws_bytes < need) return fail(HY_ERR_NOMEM, "workspace smaller than hy_workspace_bytes()");
-  int dev;
-  HY_HIP(hipGetDevice(&dev));
-  hipPointerAttribute_t attr;
-  if (hipPointerGetAttributes(&attr, dev_ws) != hipSuccess || attr.type != hipMemoryTypeDevice ||
-      attr.device != dev) {
-    (void)hipGetLastError();
-    return fail(HY_ERR_ARG, "workspace is not device memory of the current device");
-  }
-  hy_problem* p = new (std::nothrow) hy_problem();
-  if (!p) return fail(HY_ERR_NOMEM, "host allocation failed");
+namespace {
+
+// Fill a host problem object for a workspace at `ws` and the header bytes its
+// device copy must hold (descriptor and cleared counters); with refinement,
+// also the tables to upload into the workspace. No device calls.
+hy_status build_problem(const hy_config* cfg, char* ws, size_t ws_bytes, int dev, hy_problem* p,
+                        unsigned char hdr[kHeaderBytes], SmrLayout* L) {
   p->cfg = *cfg;
   p->ng = ghost_depth(cfg->recon);
   for (int d = 0; d < 3; ++d) p->nblk[d] = cfg->n[d] / cfg->block[d];
   p->ncell = (int64_t)cfg->n[0] * cfg->n[1] * cfg->n[2];
-  p->ws = (char*)dev_ws;
+  p->ws = ws;
   p->ws_bytes = ws_bytes;
   p->dp = (DevProblem*)p->ws;
   p->dc = (DevCounters*)(p->ws + sizeof(DevProblem));
@@ -604,26 +592,64 @@ hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_prob
   h.fofc_total = &p->dc->fofc_total;
   h.nstages = stages_of(cfg);
   for (int st = 1; st <= h.nstages; ++st) h.rk[st - 1] = rk_stage_of(h, st);
-  SmrLayout L;
   if (has_refine(cfg)) {
-    build_smr(cfg, L);
-    if (L.nvirt > 65535 || L.ncf > 65535 || L.nleaf > 65535) {
-      delete p;
+    build_smr(cfg, *L);
+    if (L->nvirt > 65535 || L->ncf > 65535 || L->nleaf > 65535)
       return fail(HY_ERR_ARG, "refined mesh too large (max 65535 leaves and level-change faces)");
-    }
     char* t = p->ws + kHeaderBytes + (size_t)nreg * reg_bytes(cfg) + flag_bytes(cfg);
     h.binfo = (const int32_t*)t;
-    t += align256(L.binfo.size() * 4);
+    t += align256(L->binfo.size() * 4);
     h.vinfo = (const int32_t*)t;
-    t += align256(L.vinfo.size() * 4 + 4);
+    t += align256(L->vinfo.size() * 4 + 4);
     h.rinfo = (const int32_t*)t;
-    t += align256(L.rinfo.size() * 4);
+    t += align256(L->rinfo.size() * 4);
     h.cfinfo = (const int32_t*)t;
-    h.nvirt = L.nvirt;
-    h.ncf = L.ncf;
-    for (int d = 0; d < 3; ++d) h.nroot[d] = L.nr[d];
-    h.nblocks = L.nleaf;
-    p->ncell = (int64_t)L.nleaf * h.vstride;
+    h.nvirt = L->nvirt;
+    h.ncf = L->ncf;
+    for (int d = 0; d < 3; ++d) h.nroot[d] = L->nr[d];
+    h.nblocks = L->nleaf;
+    p->ncell = (int64_t)L->nleaf * h.vstride;
+  }
+  std::memset(hdr, 0, kHeaderBytes);
+  std::memcpy(hdr, &h, sizeof h);
+  DevCounters c;
+  std::memset(&c, 0, sizeof c);
+  c.dtmin[0] = c.dtmin[1] = kInf;
+  std::memcpy(hdr + sizeof(DevProblem), &c, sizeof c);
+  default_launch(p, &p->variant, &p->kc);
+  return HY_OK;
+}
+
+}  // namespace
+
+hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_problem** out) {
+  std::string msg;
+  if (!out) return fail(HY_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!validate(cfg, msg)) return fail(HY_ERR_ARG, msg);
+  if (!dev_ws) return fail(HY_ERR_ARG, "workspace is NULL");
+  if (((uintptr_t)dev_ws) & 255) return fail(HY_ERR_ARG, "workspace must be 256-byte aligned");
+  const size_t need = hy_workspace_bytes(cfg);
+  if (ws_bytes < need) return fail(HY_ERR_NOMEM, "workspace smaller than hy_workspace_bytes()");
+  int dev;
+  HY_HIP(hipGetDevice(&dev));
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, dev_ws) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+      attr.device != dev) {
+    (void)hipGetLastError();
+    return fail(HY_ERR_ARG, "workspace is not device memory of the current device");
+  }
+  hy_problem* p = new (std::nothrow) hy_problem();
+  if (!p) return fail(HY_ERR_NOMEM, "host allocation failed");
+  unsigned char hdr[kHeaderBytes];
+  SmrLayout L;
+  hy_status st = build_problem(cfg, (char*)dev_ws, ws_bytes, dev, p, hdr, &L);
+  if (st != HY_OK) {
+    delete p;
+    return st;
+  }
+  const DevProblem& h = p->hp;
+  if (h.binfo) {
     const std::pair<const int32_t*, const std::vector<int32_t>*> tabs[4] = {
         {h.binfo, &L.binfo}, {h.vinfo, &L.vinfo}, {h.rinfo, &L.rinfo}, {h.cfinfo, &L.cfinfo}};
     for (const auto& tb : tabs)
@@ -634,20 +660,11 @@ hy_status hy_create(const hy_config* cfg, void* dev_ws, size_t ws_bytes, hy_prob
         return fail(HY_ERR_HIP, "refinement table upload failed");
       }
   }
-
-  unsigned char hdr[kHeaderBytes];
-  std::memset(hdr, 0, sizeof hdr);
-  std::memcpy(hdr, &h, sizeof h);
-  DevCounters c;
-  std::memset(&c, 0, sizeof c);
-  c.dtmin[0] = c.dtmin[1] = kInf;
-  std::memcpy(hdr + sizeof(DevProblem), &c, sizeof c);
-  if (hipMemcpy(p->ws, hdr, sizeof hdr, hipMemcpyHostToDevice) != hipSuccess ||
+  if (hipMemcpy(p->ws, hdr, kHeaderBytes, hipMemcpyHostToDevice) != hipSuccess ||
       (cfg->fofc && hipMemset(h.flags, 0, flag_bytes(cfg)) != hipSuccess)) {
     delete p;
     return fail(HY_ERR_HIP, "header upload failed");
   }
-  default_launch(p, &p->variant, &p->kc);
   *out = p;
   return HY_OK;
 }
@@ -944,3 +961,75 @@ hy_status hy_advance_timed(hy_problem* p, int32_t nsteps, void* stream, double* 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------- allocation-free entry
+// For callers that cannot allocate device memory (code under HIP graph
+// capture, tight serving loops): the problem's whole workspace lives in a
+// file-scope device array of kNoAllocBytes per GPU, held until the process
+// ends. Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in for the symbol): each device's address comes from
+// hipGetSymbolAddress on the first call there, with that device current.
+namespace {
+
+constexpr size_t kNoAllocBytes = (size_t)HY_NOALLOC_MAX_BYTES;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hy_status scratch_of(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(HY_ERR_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HY_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || ((uintptr_t)ptr & 255)) return fail(HY_ERR_HIP, "scratch symbol address unusable");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return HY_OK;
+}
+
+}  // namespace
+
+hy_status hy_advance_noalloc(const hy_config* cfg, double* U, int32_t nsteps, double t0,
+                             double* out, void* stream) {
+  std::string msg;
+  if (!validate(cfg, msg)) return fail(HY_ERR_ARG, msg);
+  if (!U) return fail(HY_ERR_ARG, "U is NULL");
+  if (nsteps < 0) return fail(HY_ERR_ARG, "nsteps must be >= 0");
+  if (!std::isfinite(t0)) return fail(HY_ERR_ARG, "t0 must be finite");
+  if (has_refine(cfg)) return fail(HY_ERR_ARG, "hy_advance_noalloc does not take refined meshes");
+  const size_t need = hy_workspace_bytes(cfg);
+  if (need > kNoAllocBytes)
+    return fail(HY_ERR_NOMEM, "problem needs " + std::to_string(need) + " workspace bytes; "
+                "hy_advance_noalloc holds at most " + std::to_string(kNoAllocBytes));
+  int dev;
+  HY_HIP(hipGetDevice(&dev));
+  char* ws = nullptr;
+  hy_status st = scratch_of(dev, &ws);
+  if (st != HY_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hy_problem p;
+  HeaderBytes hdr;
+  SmrLayout L;
+  st = build_problem(cfg, ws, kNoAllocBytes, dev, &p, hdr.b, &L);
+  if (st != HY_OK) return st;
+  {
+    DevCounters c;
+    std::memcpy(&c, hdr.b + sizeof(DevProblem), sizeof c);
+    c.time = t0;
+    std::memcpy(hdr.b + sizeof(DevProblem), &c, sizeof c);
+  }
+  // header (every counter starts cleared), state into the MeshBlockPack,
+  // first time step, the steps, result back out; kernels only
+  HY_HIP(launch_put_header(hdr, ws, s));
+  HY_HIP(launch_scatter(p.dp, U, p.hp.U, p.ncell * 5, 1, s));
+  HY_HIP(launch_dt(p.dp, p.ncell, 0, 1, s));
+  st = run_batch(std::array<hy_problem*, 1>{&p}.data(), &nsteps, 1, s, nullptr, 1);
+  if (st != HY_OK) return st;
+  HY_HIP(launch_scatter(p.dp, p.hp.U, U, p.ncell * 5, 0, s));
+  if (out) HY_HIP(launch_result(p.dp, (int)(p.steps & 1), out, s));
+  return HY_OK;
+}

@@ -122,6 +122,11 @@ struct DevCounters {
 
 static_assert(sizeof(DevProblem) + sizeof(DevCounters) <= kHeaderBytes, "header too large");
 
+// A whole header as a kernel argument (see k_put_header).
+struct HeaderBytes {
+  unsigned char b[kHeaderBytes];
+};
+
 // One problem's share of a batched stage launch (kernel arguments).
 struct BatchEntry {
   const DevProblem* p;

@@ -1600,6 +1600,23 @@ __global__ void __launch_bounds__(256) k_scatter(const DevProblem* __restrict__ 
   }
 }
 
+// Write a problem header (descriptor and counters) passed by value into the
+// workspace: the allocation-free entry point sets up its scratch workspace
+// with kernels only (no host-to-device copy).
+__global__ void __launch_bounds__(256) k_put_header(const HeaderBytes h, unsigned char* __restrict__ dst) {
+  for (int i = threadIdx.x; i < kHeaderBytes; i += blockDim.x) dst[i] = h.b[i];
+}
+
+// Time, next time step and error flag of a problem into out[0..2] (device).
+__global__ void k_result(const DevProblem* __restrict__ Pp, int slot, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const DevProblem& P = *Pp;
+    out[0] = *P.time;
+    out[1] = P.cfl * __longlong_as_double((long long)P.dtmin[slot]);
+    out[2] = *P.err ? 1.0 : 0.0;
+  }
+}
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Plain streaming copy (16 bytes per lane per iteration).
@@ -1693,6 +1710,16 @@ hipError_t launch_scatter(const DevProblem* p, const double* src, double* dst, i
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)g), dim3(256), 0, s, p, src, dst, to_blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_put_header(const HeaderBytes& h, void* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_put_header, dim3(1), dim3(256), 0, s, h, (unsigned char*)dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_result(const DevProblem* p, int slot, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_result, dim3(1), dim3(64), 0, s, p, slot, out);
   return hipGetLastError();
 }
 

@@ -17,6 +17,8 @@ hipError_t launch_dt(const DevProblem* p, int64_t ncell, int slot, int flags, hi
 hipError_t launch_scatter(const DevProblem* p, const double* src, double* dst, int64_t n,
                           int to_blocks, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t launch_put_header(const HeaderBytes& h, void* dst, hipStream_t s);
+hipError_t launch_result(const DevProblem* p, int slot, double* out, hipStream_t s);
 hipError_t launch_smr_ghost(const DevProblem* p, int stage, int ng, int nvirt, const int32_t block[3],
                             hipStream_t s);
 hipError_t launch_smr_flux(int recon, int prec, const DevProblem* p, int stage, int parity, int ncf,

@@ -71,6 +71,7 @@ SIGNATURES = {
     "hy_autotune": ([_vp, _vp, _c.c_int32, _i32p, _i32p, _dp], _c.c_int),
     "hy_copy_probe": ([_vp, _vp, _c.c_size_t, _vp], _c.c_int),
     "hy_advance_timed": ([_vp, _c.c_int32, _vp, _dp, _dp], _c.c_int),
+    "hy_advance_noalloc": ([_CP, _vp, _c.c_int32, _c.c_double, _vp, _vp], _c.c_int),
 }
 
 _lib = None
@@ -341,3 +342,23 @@ def copy_probe(dst, src, nbytes=None, stream=None):
     """Plain device-to-device streaming copy with the library's probe kernel."""
     nbytes = src.numel() * src.element_size() if nbytes is None else nbytes
     _check(lib().hy_copy_probe(_vp(dst.data_ptr()), _vp(src.data_ptr()), int(nbytes), _stream(stream)))
+
+
+NOALLOC_MAX_BYTES = 256 << 20  # HY_NOALLOC_MAX_BYTES of include/hy.h
+
+
+def advance_noalloc(pb, U, nsteps, t0=0.0, out=None, stream=None):
+    """hy_advance_noalloc: advance the device state ``U`` (a contiguous
+    float64 CUDA tensor of shape (5, nz, ny, nx)) in place by ``nsteps`` steps
+    of problem ``pb`` without any device allocation; ``out`` (a float64 CUDA
+    tensor of 3, or None) receives (t, dt_next, error flag)."""
+    torch = _torch()
+    c = make_config(pb)
+    if not (isinstance(U, torch.Tensor) and U.is_cuda and U.dtype == torch.float64
+            and U.is_contiguous() and U.numel() == 5 * int(np.prod(pb.n))):
+        raise ValueError("U must be a contiguous float64 CUDA tensor of 5 * cells elements")
+    if out is not None and not (out.is_cuda and out.dtype == torch.float64 and out.numel() >= 3):
+        raise ValueError("out must be a float64 CUDA tensor of at least 3 elements")
+    optr = _vp(out.data_ptr()) if out is not None else None
+    _check(lib().hy_advance_noalloc(_c.byref(c), _vp(U.data_ptr()), int(nsteps), float(t0), optr,
+                                    _stream(stream)))
