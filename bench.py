@@ -230,6 +230,15 @@ def main():
                       f"{t1 - t0:.1f} s wall",
         }
         assert r["status"] == 0
+        # full-size parity on the same steps: the FP64 and mixed GPU paths
+        # against the reference solver's result
+        ref_rel = rel_l1_vs_reference(hy, P, pb, nsteps, r["U"])
+        out["parity_full_size"] = {"steps": nsteps, "fp64_rel_l1_vs_oracle": ref_rel["fp64"],
+                                   "mixed_rel_l1_vs_oracle": ref_rel["mixed"],
+                                   "gates": {"fp64": 1e-12, "mixed": 1e-5}}
+        if "mixed" in out:
+            out["mixed"]["rel_l1_vs_oracle"] = ref_rel["mixed"]
+            out["mixed"]["rel_l1_vs_oracle_steps"] = nsteps
         # one host thread, on a 128^3 cut of the same workload (one step)
         threads = oracle.get_threads()
         small, _ = P.workload_turbulence_256(N=128, block=64)
@@ -251,7 +260,7 @@ def main():
         if not args.skip_schemes:
             out["schemes"] = run_schemes(run, pb, P, args.steps)
         if not args.skip_kh:
-            out["kh512"] = run_kh512(run, P)
+            out["kh512"] = run_kh512(run, P, hy, cpu=not args.skip_cpu)
         if not args.skip_refined:
             out["refined"] = run_refined(run, hy, P, value, args.steps, cpu=not args.skip_cpu)
         if not args.no_batch:
@@ -337,7 +346,21 @@ def run_refined(run, hy, P, uniform_value, steps, cpu=True):
     return out
 
 
-def run_kh512(run, P):
+def rel_l1_vs_reference(hy, P, pb, nsteps, ref):
+    """Relative L1 (five variables pooled) of the FP64 and mixed GPU paths
+    after nsteps steps from pb's initial state, against the reference
+    solver's result ``ref`` for the same steps."""
+    out = {}
+    for prec, name in ((P.FP64, "fp64"), (P.MIXED, "mixed")):
+        g = hy.Problem(pb.with_(precision=prec)).set_state()
+        g.advance(nsteps)
+        Ug = g.get_state()
+        g.close()
+        out[name] = float(np.abs(Ug - ref).sum() / np.abs(ref).sum())
+    return out
+
+
+def run_kh512(run, P, hy=None, cpu=False):
     """512^3 periodic Kelvin-Helmholtz layer in 64 MeshBlocks of 128^3, PPM4,
     10 steps: FP64 and mixed throughput."""
     log("building 512^3 Kelvin-Helmholtz")
@@ -355,6 +378,18 @@ def run_kh512(run, P):
                     "launch": list(res[P.MIXED]["launch"]),
                     "rel_l1_vs_fp64_gpu": float(np.abs(res[P.MIXED]["U"] - res[P.FP64]["U"]).sum()
                                                 / np.abs(res[P.FP64]["U"]).sum())}
+    if cpu:
+        import oracle
+        oracle.build(force=False)
+        log("kh512: one step of the reference solver for the L1 comparison")
+        t0 = time.perf_counter()
+        ref = oracle.advance(pb, 1)
+        t1 = time.perf_counter()
+        rel = rel_l1_vs_reference(hy, P, pb, 1, ref["U"])
+        out["fp64"]["rel_l1_vs_oracle"] = rel["fp64"]
+        out["mixed"]["rel_l1_vs_oracle"] = rel["mixed"]
+        out["oracle_step_s"] = t1 - t0
+        out["rel_l1_vs_oracle_steps"] = 1
     return out
 
 

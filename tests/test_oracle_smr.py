@@ -351,3 +351,20 @@ def test_ppmx_on_prolongated_plateaus_is_ill_conditioned(oracle_lib):
     assert sensitivity(P.PPMX, True) > 1e-12
     assert sensitivity(P.PLM, True) < 1e-14
     assert sensitivity(P.PPMX, False) < 1e-14
+
+
+def test_random_refined_seed1_ppmx_is_ill_conditioned(oracle_lib):
+    # The seeded refined configuration 1 (smooth fields, PPMX, RK3): minmod
+    # prolongation of a coarse extremum gives its 8 children one value, and
+    # PPMX's extremum switch is discontinuous at such exact plateaus, so a
+    # one-ulp change of half the initial values moves the reference solver's
+    # result by ~1e-10; the same mesh and data with PLM or PPM4 move by
+    # rounding only. The GPU parity gate for this case is therefore set from
+    # this sensitivity rather than at 1e-12.
+    from smr_cases import one_ulp_sensitivity, random_config, random_refined
+    assert random_config(1)[0] == P.PPMX
+    s = one_ulp_sensitivity(oracle_lib.advance, random_refined(1, oracle_lib.smr_leaves), 4)
+    assert 1e-12 < s < 1e-8
+    for recon in (P.PLM, P.PPM4):
+        pb = random_refined(1, oracle_lib.smr_leaves, recon=recon)
+        assert one_ulp_sensitivity(oracle_lib.advance, pb, 4) < 1e-14
