@@ -121,6 +121,28 @@ def _stream(stream):
     return _vp(s.cuda_stream)
 
 
+def _enter(stream, *tensors):
+    """Before the library works on ``stream`` with tensors produced on torch's
+    current stream: order ``stream`` after that work and tell the caching
+    allocator that the tensors are in use there."""
+    torch = _torch()
+    if stream is None:
+        return
+    cur = torch.cuda.current_stream()
+    if stream != cur:
+        stream.wait_stream(cur)
+        for t in tensors:
+            t.record_stream(stream)
+
+
+def _leave(stream):
+    """After enqueuing work on ``stream`` whose results torch's current stream
+    will read: order the current stream after it."""
+    torch = _torch()
+    if stream is not None and stream != torch.cuda.current_stream():
+        torch.cuda.current_stream().wait_stream(stream)
+
+
 def make_config(pb) -> HyConfig:
     """HyConfig from a ``problems.Problem``."""
     c = HyConfig()
@@ -216,6 +238,7 @@ class Problem:
         if isinstance(U, torch.Tensor) and U.is_cuda:
             t = U.to(torch.float64).contiguous()
             assert tuple(t.shape) == self.shape
+            _enter(stream, t)
             _check(lib().hy_set_state(self.h, _vp(t.data_ptr()), DEVICE, _stream(stream)))
             self._keep = t
         else:
@@ -235,7 +258,9 @@ class Problem:
         torch = _torch()
         if device:
             out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+            _enter(stream, out)
             _check(lib().hy_get_state(self.h, _vp(out.data_ptr()), DEVICE, _stream(stream)))
+            _leave(stream)
             return out
         out = np.empty(self.shape, dtype=np.float64)
         _check(lib().hy_get_state(self.h, _vp(out.ctypes.data), HOST, _stream(stream)))
@@ -360,5 +385,7 @@ def advance_noalloc(pb, U, nsteps, t0=0.0, out=None, stream=None):
     if out is not None and not (out.is_cuda and out.dtype == torch.float64 and out.numel() >= 3):
         raise ValueError("out must be a float64 CUDA tensor of at least 3 elements")
     optr = _vp(out.data_ptr()) if out is not None else None
+    _enter(stream, U, *([out] if out is not None else []))
     _check(lib().hy_advance_noalloc(_c.byref(c), _vp(U.data_ptr()), int(nsteps), float(t0), optr,
                                     _stream(stream)))
+    _leave(stream)

@@ -251,6 +251,21 @@ def test_mixed_rk3_vs_fp64_reference(hy, case):
     assert r <= 1e-5
 
 
+@pytest.mark.xfail(strict=False, reason=(
+    "FP32 primitives (6e-8 relative) cannot resolve a 1e-6 break of the blast's mirror "
+    "symmetry, where WENO-Z's tau5 is the difference of two nearly equal indicators: the "
+    "mixed path departs from FP64 at ~1e-4. Computing the indicators and weights in FP64 "
+    "from the same FP32 values leaves it at 7e-5 (CPU build of the kernel), so the loss is "
+    "in the FP32 rounding of the inputs, not in the weight arithmetic"))
+def test_mixed_wenoz_sedov_small_symmetry_break(hy):
+    pb = P.sedov(N=32, seed=3, noise=1e-6).with_(block=(16, 16, 16), recon=P.WENOZ, rk=3)
+    ref = oracle.advance(pb, 20)
+    U, _ = _run(hy, pb.with_(precision=P.MIXED), 20)
+    r = _rel(U, ref["U"])
+    print(f"[mixed sedov wenoz 1e-6 break] rel L1 vs FP64 reference {r:.3e}", flush=True)
+    assert r <= 1e-5
+
+
 @pytest.mark.parametrize("recon", [P.WENOZ, P.PPMX])
 def test_rk3_every_tile_shape_bitwise(hy, recon):
     pb = P.turbulence(N=32, seed=9, kmax=8).with_(block=(32, 32, 32), recon=recon, rk=3)
