@@ -84,7 +84,7 @@ def main():
                     help="tile variant and z-chunk as V,KC (FP64 and mixed), or 'auto' to autotune")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 48-problem Sedov batch (mixed, 50 steps)")
-    ap.add_argument("--serve", type=int, default=120, metavar="COUNT",
+    ap.add_argument("--serve", type=int, default=1000, metavar="COUNT",
                     help="serve COUNT requests of the seeded Poisson stream (0: skip)")
     ap.add_argument("--skip-kh", action="store_true", help="skip the 512^3 PPM4 workload")
     ap.add_argument("--skip-schemes", action="store_true", help="skip WENO-Z/RK3 and PPM4 at 256^3")
@@ -92,10 +92,14 @@ def main():
                     help="skip the statically refined 256^3 workload")
     ap.add_argument("--refined-only", action="store_true",
                     help="time only the statically refined workload (for profiling)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the two batch workloads (for profiling)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the 256^3 FP64 (and mixed) lines")
-    ap.add_argument("--serve-budget-gb", default="16",
+    ap.add_argument("--serve-budget-gb", default="16,8,64",
                     help="HBM budget(s) in GiB for continuous batching, comma-separated")
+    ap.add_argument("--serve-policies", default="oldest-first",
+                    help="continuous-batching policies to run (oldest-first, all), comma-separated")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -144,6 +148,12 @@ def main():
         g.close()
         sec = t1 - t0
         return dict(sec=sec, ms1=ms1, ms2=ms2, q=q, U=U, launch=launch)
+
+    if args.batch_only:
+        print(json.dumps({"batch": run_batch_workload(hy, P, torch),
+                          "batch_small": run_batch_workload(hy, P, torch, seed=5, sizes=(32, 48),
+                                                            label="small")}), flush=True)
+        return
 
     if args.refined_only:
         print(json.dumps({"refined": run_refined(run, hy, P, None, args.steps, cpu=not args.skip_cpu)}),
@@ -265,8 +275,11 @@ def main():
             out["refined"] = run_refined(run, hy, P, value, args.steps, cpu=not args.skip_cpu)
         if not args.no_batch:
             out["batch"] = run_batch_workload(hy, P, torch)
+            out["batch_small"] = run_batch_workload(hy, P, torch, seed=5, sizes=(32, 48),
+                                                    label="small")
         if args.serve:
-            out["serving"] = run_serving_workload(hy, P, args.serve, args.serve_budget_gb)
+            out["serving"] = run_serving_workload(hy, P, args.serve, args.serve_budget_gb,
+                                                  policies=args.serve_policies)
 
     print(json.dumps(out), flush=True)
 
@@ -429,14 +442,15 @@ def run_small_workload(hy, P, torch, reps=20):
             "l1_rho_vs_closed_form_over_amplitude": float(np.abs(U[0] - ex[0]).mean() / amp)}
 
 
-def run_batch_workload(hy, P, torch, count=48, seed=3):
-    """48 independent Sedov problems (sizes drawn by seed from 32..128^3),
-    outflow, PLM + HLLC, RK2, 50 steps each, mixed precision: aggregate
-    cell-updates/s with one launch per RK stage for all problems, against the
-    same problems advanced one at a time."""
-    pbs, steps = P.workload_sedov_batch(count=count, seed=seed)
+def run_batch_workload(hy, P, torch, count=48, seed=3, sizes=None, label="sedov_c4"):
+    """``count`` independent Sedov problems (sizes drawn by seed, by default
+    from 32..128^3), outflow, PLM + HLLC, RK2, 50 steps each, mixed precision:
+    aggregate cell-updates/s with one launch per RK stage for all problems,
+    against the same problems advanced one at a time (also per size class)."""
+    kw = {} if sizes is None else {"sizes": sizes}
+    pbs, steps = P.workload_sedov_batch(count=count, seed=seed, **kw)
     cells = sum(p.cells for p in pbs)
-    log(f"batch: {count} Sedov problems, {cells} cells, {steps} steps")
+    log(f"batch {label}: {count} Sedov problems, {cells} cells, {steps} steps")
     gs = [hy.Problem(p) for p in pbs]
     tuned = {}
     for g, p in zip(gs, pbs):       # autotune once per size class
@@ -447,11 +461,16 @@ def run_batch_workload(hy, P, torch, count=48, seed=3):
         else:
             g.set_launch(*tuned[key][:2])
     torch.cuda.synchronize()
-    # one at a time, each in its own tuned shape
+    # one at a time, each in its own tuned shape; time per size class too
+    per_class = {}
     t0 = time.perf_counter()
-    for g in gs:
+    for g, p in zip(gs, pbs):
+        t1 = time.perf_counter()
         g.advance(steps)
         torch.cuda.synchronize()
+        c = per_class.setdefault(f"{p.n[0]}^3", [0, 0.0])
+        c[0] += 1
+        c[1] += time.perf_counter() - t1
     t_one = time.perf_counter() - t0
     # the batch shares one tile shape per launch: tune it for the batch as a
     # whole (each problem keeps its own z-chunk), timing two batched steps
@@ -495,60 +514,74 @@ def run_batch_workload(hy, P, torch, count=48, seed=3):
     floors = sum(g.query()["floor_hits"] for g in gs)
     for g in gs:
         g.close()
+    n_of = {f"{p.n[0]}^3": p.cells for p in pbs}
     return {
+        "workload": f"{count} Sedov problems, sizes drawn from "
+                    f"{sorted(set(int(p.n[0]) for p in pbs))} (cubed), outflow, PLM+HLLC, SSP-RK2, mixed, "
+                    f"{steps} steps each, seed {seed}",
         "value": cells * steps / t_batch,
         "unit": "cell-updates/s",
         "graph_replay": cells * steps / t_graph,
         "graph_equals_eager": bool(same),
         "one_by_one": cells * steps / t_one,
         "speedup": t_one / t_batch,
+        "speedup_graph": t_one / t_graph,
         "problems": count,
         "cells": cells,
         "steps": steps,
         "dtype": "mixed",
+        "one_by_one_per_class": {k: {"problems": v[0], "cell_updates_per_s": v[0] * n_of[k] * steps / v[1],
+                                     "us_per_step": 1e6 * v[1] / (v[0] * steps)}
+                                 for k, v in sorted(per_class.items(), key=lambda kv: n_of[kv[0]])},
         "size_classes": {f"{k[0]}^3": list(v[:2]) for k, v in tuned.items()},
         "batch_tile_variant": list(hy.variants()[best[1]]),
         "floor_hits": floors,
     }
 
 
-def run_serving_workload(hy, P, count, budgets_gb, seed=4, epoch=10):
+def run_serving_workload(hy, P, count, budgets_gb, seed=4, epoch=10, calib=200,
+                         policies="oldest-first"):
     """Poisson stream of Sod / KH / Sedov requests (32^3..256^3, 10..200
     steps, FP64 or mixed), admitted by an HBM budget: continuous batching
-    against one request at a time. Initial states are generated before the
-    runs; the arrival rate is 0.8 / (mean service time of the one-at-a-time
-    path over all the requests, all queued at once, results fetched and
-    digested as in the measured runs), so the offered load is 80% of what
-    that path can serve."""
+    against one request at a time. Initial states are generated by the
+    client's thread pool ahead of their arrival (a bounded amount of host
+    memory; generating all of them first would take ~150 GiB for 1000
+    requests). The arrival rate is 0.8 / (mean service time of the
+    one-at-a-time path over the first ``calib`` requests, all queued at once,
+    results fetched and digested as in the measured runs), so the offered load
+    is 80% of what that path can serve. Every run serves the same ``count``
+    requests; a served result is compared with the one-at-a-time result by
+    digest."""
     from paper_2409_16053_amd import serve
-    log(f"serving: generating {count} initial states")
-    inputs = serve.generate_inputs(seed, count)
-    calib = count
-    probe = serve.make_stream(seed, calib, rate=1e9, inputs=inputs)
+    calib = min(calib, count)
+    probe = serve.make_stream(seed, calib, rate=1e9)
+    log(f"serving: calibrating on {calib} requests one at a time")
     t0 = time.perf_counter()
     serve.run_fifo(probe, keep="digest", client_threads=16)  # the measured runs' own work
     mean_service = (time.perf_counter() - t0) / calib
     rate = 0.8 / mean_service
     log(f"serving: mean one-at-a-time service {mean_service * 1e3:.1f} ms -> rate {rate:.1f}/s")
-    fifo = serve.run_fifo(serve.make_stream(seed, count, rate, inputs=inputs), keep="digest",
-                          client_threads=16)
+    log(f"serving: {count} requests one at a time")
+    prog = lambda d, n: log(f"serving: {d}/{n} done")
+    fifo = serve.run_fifo(serve.make_stream(seed, count, rate), keep="digest", client_threads=16,
+                          progress=prog)
     sf = serve.summarize(fifo)
     budgets = [float(b) for b in str(budgets_gb).split(",")]
     runs = []
-    for budget_gb in budgets:
-        log(f"serving: continuous batching, budget {budget_gb} GiB")
-        srv = serve.Server(budget_bytes=int(budget_gb * 2 ** 30), epoch_steps=epoch, keep="digest",
-                           client_threads=16)
-        cont = srv.run(serve.make_stream(seed, count, rate, inputs=inputs))
-        runs.append({"budget_gb": budget_gb, "continuous": serve.summarize(cont),
-                     "peak_resident_gb": srv.peak_bytes / 2 ** 30, "epochs": srv.epochs,
-                     "results_equal_alone": bool(all(a.digest == b.digest for a, b in zip(cont, fifo)))})
+    for policy in str(policies).split(","):
+        for budget_gb in budgets:
+            log(f"serving: {count} requests, continuous batching ({policy}), budget {budget_gb} GiB")
+            srv = serve.Server(budget_bytes=int(budget_gb * 2 ** 30), epoch_steps=epoch, keep="digest",
+                               client_threads=16, policy=policy)
+            cont = srv.run(serve.make_stream(seed, count, rate), progress=prog)
+            runs.append({"policy": policy, "budget_gb": budget_gb, "continuous": serve.summarize(cont),
+                         "peak_resident_gb": srv.peak_bytes / 2 ** 30, "epochs": srv.epochs,
+                         "results_equal_alone": bool(all(a.digest == b.digest for a, b in zip(cont, fifo)))})
     out = {"requests": count, "rate_per_s": rate, "mean_service_ms_one_at_a_time": mean_service * 1e3,
-           "calibration_requests": calib,
-           "epoch_steps": epoch, "fifo": sf}
+           "calibration_requests": calib, "epoch_steps": epoch, "fifo": sf}
     out.update(runs[0])
     if len(runs) > 1:
-        out["budget_sweep"] = runs
+        out["sweep"] = runs
     return out
 
 

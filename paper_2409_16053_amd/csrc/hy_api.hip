@@ -265,6 +265,7 @@ void default_launch(const hy_problem* p, int* variant, int* kc) {
 struct Plan {
   int variant, recon, prec;
   std::vector<int> idx;  // problems in this launch group
+  std::vector<int> kc;   // z-chunk per problem (indexed like the batch)
 };
 
 hy_status check_batch(hy_problem* const* ps, const int32_t* nsteps, int32_t n) {
@@ -298,6 +299,33 @@ std::vector<Plan> make_plans(hy_problem* const* ps, int32_t n) {
     for (int q : pl.idx)
       if (ps[q]->ncell > best) { best = ps[q]->ncell; pl.variant = ps[q]->variant; }
   }
+  // z-chunks: each problem's own (tuned or default) chunk, lengthened to a
+  // common minimum K while the group still has >= 2048 tiles. A problem
+  // alone marches short chunks only to fill the chip; in a batch of many
+  // small problems the others fill it, and short chunks would re-load the
+  // z stencil (2 NG extra planes per chunk) for nothing.
+  for (auto& pl : plans) {
+    int tx, ty;
+    stage_variant_shape(pl.variant, &tx, &ty);
+    auto kc_of = [&](int q, int K) {
+      return std::max(1, std::min(std::max(ps[q]->kc, K), ps[q]->cfg.block[2]));
+    };
+    auto tiles = [&](int K) {
+      int64_t t = 0;
+      for (int q : pl.idx) {
+        const hy_problem* p = ps[q];
+        const int64_t cols = (int64_t)((p->cfg.block[0] + tx - 1) / tx) * ((p->cfg.block[1] + ty - 1) / ty);
+        t += (int64_t)p->hp.nblocks * cols * ((p->cfg.block[2] + kc_of(q, K) - 1) / kc_of(q, K));
+      }
+      return t;
+    };
+    int K = 1;
+    if (pl.idx.size() > 1)
+      for (int cand = 64; cand > 1; cand /= 2)
+        if (tiles(cand) >= 2048) { K = cand; break; }
+    pl.kc.assign(n, 1);
+    for (int q : pl.idx) pl.kc[q] = kc_of(q, K);
+  }
   return plans;
 }
 
@@ -321,7 +349,7 @@ hy_status launch_group(hy_problem* const* ps, const std::vector<int>& act, const
       e.tile0 = (int32_t)tiles;
       e.ntx = (p->cfg.block[0] + tx - 1) / tx;
       e.nty = (p->cfg.block[1] + ty - 1) / ty;
-      e.kc = std::max(1, std::min(p->kc, p->cfg.block[2]));
+      e.kc = pl.kc[q];
       e.ntz = (p->cfg.block[2] + e.kc - 1) / e.kc;
       e.parity = (int32_t)(step_of[q] & 1);
       e.flags = flags;

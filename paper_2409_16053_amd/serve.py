@@ -4,11 +4,12 @@ Requests (a problem, a step count, an arrival time) arrive as a Poisson
 stream. The server admits waiting requests in arrival order whenever the sum
 of resident workspaces stays within an HBM budget (each problem's workspace
 is exactly ``hy.workspace_bytes``, because the library allocates nothing
-else), keeps admitted states resident, and advances all resident problems
+else), keeps admitted states resident, and advances resident problems
 together in epochs of at most ``epoch_steps`` steps with ``hy.batch_advance``
-(one launch per RK stage and kernel for the whole resident set). Requests
-that arrive while others run join the next epoch as soon as memory frees up,
-so their work shares launches with the running ones.
+(one launch per RK stage and kernel for all problems of the epoch). Requests
+that arrive while others run join an epoch as soon as memory frees up and the
+scheduling policy (below) lets them in, so their work shares launches with the
+running ones.
 
 Transfers overlap compute: epochs run on a compute stream, while initial
 states go up and results come back through page-locked buffers on separate
@@ -20,6 +21,17 @@ Initial states are produced by a client-side thread pool (the stand-in for
 clients sending data) ahead of the arrival time; their generation is not part
 of the measured latency, which runs from the scheduled arrival to the result
 being on the host.
+
+Scheduling policy ("oldest-first", the default): each epoch advances the
+oldest resident problem by its full epoch, and younger resident problems join
+it, in arrival order, while the epoch's work (cells x steps) stays within
+(1 + slack) x max(the oldest's work, a floor of ``min_epoch_work``). The
+oldest request therefore runs at close to its solo speed, as it would on the
+one-at-a-time path (which bounds the latency of the largest requests), while
+smaller requests ride in the slack instead of queueing behind it. Policy
+"all" advances every resident problem in every epoch (processor sharing: the
+best median, but a large request then shares the GPU with everything that
+arrives while it runs).
 
 Every problem's per-cell arithmetic is independent of which other problems
 share a launch, so a served result equals the result of running the request
@@ -158,9 +170,15 @@ class Server:
     """Continuous batching by HBM budget (see the module docstring)."""
 
     def __init__(self, budget_bytes: int, epoch_steps: int = 10, client_threads: int = 8,
-                 tuned: dict | None = None, keep: str = "array"):
+                 tuned: dict | None = None, keep: str = "array", policy: str = "oldest-first",
+                 slack: float = 0.25, min_epoch_work: float = 4e7):
+        if policy not in ("oldest-first", "all"):
+            raise ValueError("policy must be 'oldest-first' or 'all'")
         self.budget = int(budget_bytes)
         self.epoch = int(epoch_steps)
+        self.policy = policy
+        self.slack = float(slack)
+        self.min_work = float(min_epoch_work)
         self.client_threads = client_threads
         self.tuned = tuned if tuned is not None else {}
         self.keep = keep
@@ -172,9 +190,24 @@ class Server:
         if key in self.tuned:
             g.set_launch(*self.tuned[key])
 
-    def run(self, requests):
+    def _select(self, resident):
+        """Indices (into the arrival-ordered resident list) of the problems that
+        advance in this epoch."""
+        if self.policy == "all":
+            return list(range(len(resident)))
+        work = [r.pb.cells * min(rem, self.epoch) for r, _, rem in resident]
+        cap = (1.0 + self.slack) * max(work[0], self.min_work)
+        sel, tot = [], 0.0
+        for i, w in enumerate(work):
+            if not sel or tot + w <= cap:
+                sel.append(i)
+                tot += w
+        return sel
+
+    def run(self, requests, progress=None):
         """Serve ``requests`` in real time; returns them sorted by arrival with
-        status, admission/completion times and results (or digests) filled in."""
+        status, admission/completion times and results (or digests) filled in.
+        ``progress(done, total)`` is called after every 100th completion."""
         import torch
         reqs = sorted(requests, key=lambda r: r.arrival)
         client = _Client(reqs, threads=self.client_threads)
@@ -185,6 +218,7 @@ class Server:
         queue = collections.deque()
         admitting, resident, retiring, inflight = [], [], [], collections.deque()
         used = 0
+        finished = 0
         t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0
         try:
@@ -237,17 +271,19 @@ class Server:
                 if resident:
                     while len(inflight) >= 2:
                         inflight.popleft().synchronize()
-                    ks = [min(rem, self.epoch) for _, _, rem in resident]
-                    hy.batch_advance([g for _, g, _ in resident], ks, stream=compute)
+                    sel = self._select(resident)
+                    ks = [min(resident[i][2], self.epoch) for i in sel]
+                    hy.batch_advance([resident[i][1] for i in sel], ks, stream=compute)
                     ev_c = torch.cuda.Event()
                     ev_c.record(compute)
                     inflight.append(ev_c)
                     self.epochs += 1
                     keep = []
-                    for item, k in zip(resident, ks):
-                        item[2] -= k
+                    step_of = dict(zip(sel, ks))
+                    for i, item in enumerate(resident):
+                        item[2] -= step_of.get(i, 0)
                         r, g, rem = item
-                        if rem == 0:
+                        if i in step_of and rem == 0:
                             down.wait_event(ev_c)
                             out = torch.empty(g.shape, dtype=torch.float64, pin_memory=True)
                             g.get_state_pinned(out, stream=down)
@@ -270,6 +306,9 @@ class Server:
                         r.t_done = clock()
                         client.finish(r, out, self.keep)
                         progressed = True
+                        finished += 1
+                        if progress and finished % 100 == 0:
+                            progress(finished, len(reqs))
                     else:
                         still.append((r, g, ev_r, out))
                 retiring = still
@@ -288,9 +327,10 @@ class Server:
         return reqs
 
 
-def run_fifo(requests, tuned=None, client_threads=8, keep="array"):
+def run_fifo(requests, tuned=None, client_threads=8, keep="array", progress=None):
     """The plain path: one request at a time in arrival order, the same
-    page-locked transfers, no overlap between requests."""
+    page-locked transfers, no overlap between requests. ``progress(done,
+    total)`` is called after every 100th completion."""
     import torch
     tuned = tuned or {}
     reqs = sorted(requests, key=lambda r: r.arrival)
@@ -321,6 +361,8 @@ def run_fifo(requests, tuned=None, client_threads=8, keep="array"):
             g.close()
             r.t_done = clock()
             client.finish(r, out, keep)
+            if progress and (r.index + 1) % 100 == 0:
+                progress(r.index + 1, len(reqs))
     finally:
         client.close()
     return reqs

@@ -31,11 +31,12 @@ def _stream(count, rate, max_n=64, seed=21):
     return reqs
 
 
-def test_continuous_batching_equals_alone(hy):
+@pytest.mark.parametrize("policy", ["oldest-first", "all"])
+def test_continuous_batching_equals_alone(hy, policy):
     from paper_2409_16053_amd import serve
     reqs = _stream(14, rate=400.0)
     budget = 3 * max(r.ws_bytes for r in reqs)
-    srv = serve.Server(budget_bytes=budget, epoch_steps=7, client_threads=4)
+    srv = serve.Server(budget_bytes=budget, epoch_steps=7, client_threads=4, policy=policy)
     served = srv.run(reqs)
     assert all(r.status == hy.HY_OK for r in served)
     assert srv.peak_bytes <= budget
