@@ -48,7 +48,8 @@ typedef enum {
   HY_ERR_NOMEM = 2,  /* workspace too small or host allocation failed         */
   HY_ERR_HIP = 3,    /* a HIP runtime call failed                             */
   HY_ERR_STATE = 4,  /* a non-finite value or rho <= 0 was seen on the device */
-  HY_ERR_BUDGET = 5  /* reserved for callers that enforce a memory budget     */
+  HY_ERR_BUDGET = 5  /* never returned by the library: the serving layer
+                        (serve.py) marks requests it refuses by budget      */
 } hy_status;
 
 enum { HY_BC_PERIODIC = 0, HY_BC_OUTFLOW = 1 };
