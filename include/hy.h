@@ -8,7 +8,7 @@
  * uniform Cartesian grid (Sec. 2, "Cartesian coordinates only") cut into
  * equal MeshBlocks that are processed together as one MeshBlockPack
  * (Sec. 2, "MeshBlockPacks"; "Data locality"), optionally with a box of
- * MeshBlocks refined once (static mesh refinement, hy_config.refine_*). Each step runs the paper's
+ * MeshBlocks refined once (static mesh refinement, hy_config.refine). Each step runs the paper's
  * reconstruct-solve-advance sequence (Sec. 3): ghost zones (Sec. 2,
  * "Boundary conditions"), cons-to-prim, PLM, PPM4, PPMX or WENO-Z
  * reconstruction on primitives, HLLC fluxes in x, y and z, flux divergence
@@ -55,6 +55,7 @@ typedef enum {
 enum { HY_BC_PERIODIC = 0, HY_BC_OUTFLOW = 1 };
 enum { HY_PLM = 0, HY_PPM4 = 1, HY_WENOZ = 2, HY_PPMX = 3 };
 enum { HY_FP64 = 0, HY_MIXED = 1 };
+#define HY_MAX_REFINE_BOXES 8
 
 /* Problem definition (Sec. 2 mesh and boundaries; Sec. 3 algorithms).
  *  n[3]        global interior cells (nx, ny, nz), each >= 1.
@@ -87,12 +88,16 @@ enum { HY_FP64 = 0, HY_MIXED = 1 };
  *              and RK4 add a third state register to the workspace.
  *  rho_floor, p_floor  floors applied to the primitive state only (U is
  *              never modified by a floor); each firing is counted.
- *  refine_lo[3], refine_hi[3]  static mesh refinement (Sec. 2: MeshBlocks
- *              of equal cell count on a tree of levels): the root blocks
- *              (the n / block grid) with refine_lo <= index < refine_hi on
- *              every axis are refined once, each into 8 blocks of block[]
- *              cells at half the cell width. An empty box (refine_lo >=
- *              refine_hi on any axis) means no refinement. With refinement,
+ *  nrefine, refine[HY_MAX_REFINE_BOXES][2][3]  static mesh refinement
+ *              (Sec. 2: MeshBlocks of equal cell count on a tree of levels):
+ *              a root block (of the n / block grid) is refined once, into 8
+ *              blocks of block[] cells at half the cell width, when it lies
+ *              in any of the first nrefine boxes, box b covering the root
+ *              indices refine[b][0][d] <= index < refine[b][1][d] on every
+ *              axis d. nrefine = 0 means no refinement; each box must be
+ *              non-empty and inside the root grid; boxes may overlap or
+ *              touch (two levels keep face neighbours within one level of
+ *              each other for any union). With refinement,
  *              block[] must be even and >= twice the ghost depth, and fofc
  *              must be 0. Ghost cells across a level change hold the coarse
  *              mean of the 8 fine cells (restriction) or, on the fine side,
@@ -113,7 +118,8 @@ typedef struct {
   int32_t fofc;
   int32_t rk;
   double rho_floor, p_floor;
-  int32_t refine_lo[3], refine_hi[3];
+  int32_t nrefine;
+  int32_t refine[HY_MAX_REFINE_BOXES][2][3];
 } hy_config;
 
 /* Leaf blocks of a configuration's mesh, in the order of the leaf-major

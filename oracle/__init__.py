@@ -46,22 +46,40 @@ class Params(ctypes.Structure):
     ]
 
 
+MAX_BOXES = 8
+
+
 class Smr(ctypes.Structure):
     _fields_ = [
         ("block", ctypes.c_int32 * 3),
-        ("lo", ctypes.c_int32 * 3),
-        ("hi", ctypes.c_int32 * 3),
+        ("nbox", ctypes.c_int32),
+        ("box", ((ctypes.c_int32 * 3) * 2) * MAX_BOXES),
     ]
 
 
+def _boxes(refine):
+    """The refined boxes of ``Problem.refine``: one box ((lo), (hi)) or a
+    sequence of them."""
+    if refine is None:
+        return []
+    if len(refine) == 2 and all(np.isscalar(x) for x in refine[0]):
+        return [refine]
+    return list(refine)
+
+
 def smr_params(pb) -> Smr:
-    """ctypes refinement block (block size and refined box) of a problem."""
+    """ctypes refinement block (block size and refined boxes) of a problem."""
     S = Smr()
-    lo, hi = pb.refine if pb.refine is not None else ((0, 0, 0), (0, 0, 0))
+    boxes = _boxes(pb.refine)
+    if len(boxes) > MAX_BOXES:
+        raise ValueError(f"at most {MAX_BOXES} refined boxes")
+    S.nbox = len(boxes)
     for d in range(3):
         S.block[d] = int(pb.block[d])
-        S.lo[d] = int(lo[d])
-        S.hi[d] = int(hi[d])
+    for b, (lo, hi) in enumerate(boxes):
+        for d in range(3):
+            S.box[b][0][d] = int(lo[d])
+            S.box[b][1][d] = int(hi[d])
     return S
 
 

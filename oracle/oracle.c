@@ -850,8 +850,10 @@ int or_fill_ghosts(const or_params* p, const double* Uin, double* Uout) {
  * conservative).
  *
  * The mesh: root blocks of block[] cells tile the root grid p->n. The root
- * blocks inside the box [lo, hi) (root-block units per axis) are refined once
- * into 8 children of block[] cells at half the cell width (level 1). Leaves
+ * blocks inside any of the boxes [lo, hi) (root-block units per axis) are
+ * refined once into 8 children of block[] cells at half the cell width
+ * (level 1); with two levels, face neighbours differ by at most one level
+ * whatever the boxes, so any union of boxes is a valid mesh. Leaves
  * are ordered root by root, x fastest; a refined root contributes its
  * children with the child's x offset fastest, then y, then z. The state is
  * U[leaf][5][bz][by][bx], x fastest.
@@ -872,10 +874,13 @@ int or_fill_ghosts(const or_params* p, const double* Uin, double* Uout) {
  * A coarse face shared with 4 fine faces takes the mean of their 4 fluxes,
  * summed in pairs along the lower transverse axis first.
  * ---------------------------------------------------------------------- */
+#define OR_MAX_BOXES 8
+
 typedef struct {
-  int32_t block[3];  /* cells per block, even and >= 2 * ghosts per axis */
-  int32_t lo[3];     /* refined root blocks: lo <= root index < hi per axis */
-  int32_t hi[3];     /* (no refinement when the box is empty)             */
+  int32_t block[3];                  /* cells per block, even and >= 2 * ghosts per axis */
+  int32_t nbox;                      /* refined boxes, 0..OR_MAX_BOXES (0: none)          */
+  int32_t box[OR_MAX_BOXES][2][3];   /* box b refines the root blocks with               */
+                                     /* box[b][0][d] <= root index < box[b][1][d]        */
 } or_smr;
 
 typedef struct {
@@ -899,14 +904,15 @@ static int smr_init(smr_mesh* m, const or_params* p, const or_smr* s) {
   memset(m, 0, sizeof *m);
   m->p = *p;
   const int g = or_nghost(p->recon);
-  int empty = 0;
+  if (s->nbox < 0 || s->nbox > OR_MAX_BOXES) return OR_ERR_ARG;
   for (int d = 0; d < 3; ++d) {
     m->b[d] = s->block[d];
     if (m->b[d] < 2 * g || (m->b[d] & 1) || p->n[d] % m->b[d]) return OR_ERR_ARG;
     if ((p->bc[d][0] == OR_PERIODIC) != (p->bc[d][1] == OR_PERIODIC)) return OR_ERR_ARG;
     m->nr[d] = p->n[d] / m->b[d];
-    if (s->lo[d] < 0 || s->hi[d] > m->nr[d]) return OR_ERR_ARG;
-    if (s->lo[d] >= s->hi[d]) empty = 1;
+    for (int b = 0; b < s->nbox; ++b)
+      if (s->box[b][0][d] < 0 || s->box[b][1][d] > m->nr[d] || s->box[b][0][d] >= s->box[b][1][d])
+        return OR_ERR_ARG;
   }
   m->nroot = m->nr[0] * m->nr[1] * m->nr[2];
   m->rref = calloc((size_t)m->nroot, sizeof(int));
@@ -917,8 +923,10 @@ static int smr_init(smr_mesh* m, const or_params* p, const or_smr* s) {
     for (int ry = 0; ry < m->nr[1]; ++ry)
       for (int rx = 0; rx < m->nr[0]; ++rx) {
         const int r = rx + m->nr[0] * (ry + m->nr[1] * rz);
-        const int in = !empty && rx >= s->lo[0] && rx < s->hi[0] && ry >= s->lo[1] &&
-                       ry < s->hi[1] && rz >= s->lo[2] && rz < s->hi[2];
+        int in = 0;
+        for (int b = 0; b < s->nbox; ++b)
+          in |= rx >= s->box[b][0][0] && rx < s->box[b][1][0] && ry >= s->box[b][0][1] &&
+                ry < s->box[b][1][1] && rz >= s->box[b][0][2] && rz < s->box[b][1][2];
         m->rref[r] = in;
         m->rleaf[r] = nleaf;
         nleaf += in ? 8 : 1;

@@ -67,11 +67,18 @@ int stages_of(const hy_config* c) {
 }
 int registers_of(const hy_config* c) { return c->rk >= 3 ? 3 : 2; }
 
-// Static refinement: a non-empty box of refined root blocks.
-bool has_refine(const hy_config* c) {
-  for (int d = 0; d < 3; ++d)
-    if (c->refine_lo[d] >= c->refine_hi[d]) return false;
-  return true;
+// Static refinement: at least one box of refined root blocks.
+bool has_refine(const hy_config* c) { return c->nrefine > 0; }
+
+// Root block (rx, ry, rz) lies in one of the refined boxes.
+bool root_refined(const hy_config* c, int rx, int ry, int rz) {
+  const int r[3] = {rx, ry, rz};
+  for (int b = 0; b < c->nrefine; ++b) {
+    bool in = true;
+    for (int d = 0; d < 3; ++d) in = in && r[d] >= c->refine[b][0][d] && r[d] < c->refine[b][1][d];
+    if (in) return true;
+  }
+  return false;
 }
 
 bool validate(const hy_config* c, std::string& msg) {
@@ -103,6 +110,10 @@ bool validate(const hy_config* c, std::string& msg) {
     msg = "floors must be finite and >= 0";
     return false;
   }
+  if (c->nrefine < 0 || c->nrefine > HY_MAX_REFINE_BOXES) {
+    msg = "nrefine must be in [0, HY_MAX_REFINE_BOXES]";
+    return false;
+  }
   if (has_refine(c)) {
     if (c->fofc) { msg = "fofc cannot be combined with mesh refinement"; return false; }
     for (int d = 0; d < 3; ++d) {
@@ -110,9 +121,15 @@ bool validate(const hy_config* c, std::string& msg) {
         msg = "with refinement, block must be even and >= twice the ghost depth";
         return false;
       }
-      if (c->refine_lo[d] < 0 || c->refine_hi[d] > c->n[d] / c->block[d]) {
-        msg = "refined box outside the root block grid";
-        return false;
+      for (int b = 0; b < c->nrefine; ++b) {
+        if (c->refine[b][0][d] < 0 || c->refine[b][1][d] > c->n[d] / c->block[d]) {
+          msg = "refined box outside the root block grid";
+          return false;
+        }
+        if (c->refine[b][0][d] >= c->refine[b][1][d]) {
+          msg = "refined box is empty";
+          return false;
+        }
       }
     }
   }
@@ -143,8 +160,7 @@ void build_smr(const hy_config* c, SmrLayout& L) {
     for (int ry = 0; ry < L.nr[1]; ++ry)
       for (int rx = 0; rx < L.nr[0]; ++rx) {
         const int r = rx + L.nr[0] * (ry + L.nr[1] * rz);
-        const bool ref = rx >= c->refine_lo[0] && rx < c->refine_hi[0] && ry >= c->refine_lo[1] &&
-                         ry < c->refine_hi[1] && rz >= c->refine_lo[2] && rz < c->refine_hi[2];
+        const bool ref = root_refined(c, rx, ry, rz);
         L.rinfo[2 * r] = ref;
         L.rinfo[2 * r + 1] = (int32_t)leaf.size();
         if (!ref) {

@@ -19,6 +19,7 @@ HY_OK, HY_ERR_ARG, HY_ERR_NOMEM, HY_ERR_HIP, HY_ERR_STATE, HY_ERR_BUDGET = range
 PERIODIC, OUTFLOW = 0, 1
 PLM, PPM4, WENOZ, PPMX = 0, 1, 2, 3
 FP64, MIXED = 0, 1
+MAX_REFINE_BOXES = 8  # HY_MAX_REFINE_BOXES of include/hy.h
 HOST, DEVICE, HOST_PINNED = 0, 1, 2
 
 # (name, argtypes, restype) of every entry point declared in include/hy.h
@@ -42,8 +43,8 @@ class HyConfig(_c.Structure):
         ("rk", _c.c_int32),
         ("rho_floor", _c.c_double),
         ("p_floor", _c.c_double),
-        ("refine_lo", _c.c_int32 * 3),
-        ("refine_hi", _c.c_int32 * 3),
+        ("nrefine", _c.c_int32),
+        ("refine", ((_c.c_int32 * 3) * 2) * MAX_REFINE_BOXES),
     ]
 
 
@@ -162,11 +163,15 @@ def make_config(pb) -> HyConfig:
     c.rk = int(getattr(pb, "rk", 2))
     c.rho_floor = float(pb.rho_floor)
     c.p_floor = float(pb.p_floor)
-    ref = getattr(pb, "refine", None)
-    if ref is not None:
+    from .problems import refine_boxes
+    boxes = refine_boxes(getattr(pb, "refine", None))
+    if len(boxes) > MAX_REFINE_BOXES:
+        raise HydroError(HY_ERR_ARG, f"at most {MAX_REFINE_BOXES} refined boxes")
+    c.nrefine = len(boxes)
+    for b, (lo, hi) in enumerate(boxes):
         for d in range(3):
-            c.refine_lo[d] = int(ref[0][d])
-            c.refine_hi[d] = int(ref[1][d])
+            c.refine[b][0][d] = int(lo[d])
+            c.refine[b][1][d] = int(hi[d])
     return c
 
 

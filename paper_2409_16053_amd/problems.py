@@ -56,7 +56,8 @@ class Problem:
     p_floor: float = 1e-13
     fofc: int = 0                 # first-order flux correction (Sec. 3) on/off
     rk: int = 2                   # SSP-RK order (Sec. 3): 1, 2, 3 or 4 (SSPRK(10,4))
-    refine: tuple | None = None   # ((lo), (hi)) root blocks refined once; U is then
+    refine: tuple | None = None   # ((lo), (hi)) root blocks refined once, or a tuple of
+                                  # such boxes (their union is refined); U is then
                                   # leaf-major [leaf][5][bz][by][bx] (see to_leaves)
     name: str = ""
     meta: dict = field(default_factory=dict)
@@ -588,15 +589,26 @@ def from_leaves(UL, leaves, block, level):
     return {(int(r[1]), int(r[2]), int(r[3])): UL[q] for q, r in enumerate(lv) if r[0] == level}
 
 
+def refine_boxes(refine):
+    """The refined boxes of ``Problem.refine`` as a list of ((lo), (hi)) in
+    root blocks: ``refine`` is one box or a sequence of boxes."""
+    if refine is None:
+        return []
+    if len(refine) == 2 and all(np.isscalar(x) for x in refine[0]):
+        return [(tuple(int(x) for x in refine[0]), tuple(int(x) for x in refine[1]))]
+    return [(tuple(int(x) for x in b[0]), tuple(int(x) for x in b[1])) for b in refine]
+
+
 def refined(make, refine, leaves):
     """A problem on a statically refined mesh. ``make(s)`` builds the uniform
     problem at s times the root resolution (s = 1, 2) on the same domain with
-    the same block size; ``refine`` = ((lo), (hi)) in root blocks; ``leaves``
-    fixes the leaf order. Each leaf's cells are sampled from the problem at
-    its own resolution."""
+    the same block size; ``refine`` = ((lo), (hi)) in root blocks, or a
+    sequence of such boxes; ``leaves`` fixes the leaf order. Each leaf's cells
+    are sampled from the problem at its own resolution."""
     p1 = make(1)
     lv = np.asarray(leaves).reshape(-1, 4)
     p2 = make(2) if (lv[:, 0] == 1).any() else None
     UL = to_leaves(p1.U, None if p2 is None else p2.U, lv, p1.block)
-    return p1.with_(U=UL, refine=(tuple(refine[0]), tuple(refine[1])),
+    boxes = refine_boxes(refine)
+    return p1.with_(U=UL, refine=boxes[0] if len(boxes) == 1 else tuple(boxes),
                     name=(p1.name + " refined").strip())

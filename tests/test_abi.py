@@ -89,7 +89,11 @@ def _slab_faces(lv, nr, periodic):
 
 
 @pytest.mark.parametrize("box,periodic", [(((1, 0, 1), (3, 2, 2)), True), (((0, 0, 0), (1, 1, 1)), False),
-                                          (((0, 0, 0), (4, 3, 2)), True), (((2, 1, 0), (3, 3, 2)), False)])
+                                          (((0, 0, 0), (4, 3, 2)), True), (((2, 1, 0), (3, 3, 2)), False),
+                                          ((((0, 0, 0), (2, 1, 1)), ((1, 1, 0), (2, 3, 1)),
+                                            ((3, 2, 1), (4, 3, 2))), True),
+                                          ((((0, 0, 0), (1, 1, 1)), ((1, 1, 1), (2, 2, 2)),
+                                            ((2, 0, 0), (3, 1, 1)), ((3, 1, 1), (4, 2, 2))), False)])
 def test_refined_leaves_and_workspace_without_gpu(box, periodic):
     import oracle
     from paper_2409_16053_amd import hy
@@ -106,10 +110,13 @@ def test_refined_leaves_and_workspace_without_gpu(box, periodic):
 
 
 @pytest.mark.parametrize("bad", [dict(block=(9, 8, 8), n=(36, 24, 16)), dict(fofc=1),
-                                 dict(refine=((0, 0, 0), (5, 1, 1))), dict(recon=3, block=(4, 8, 8))])
+                                 dict(refine=((0, 0, 0), (5, 1, 1))), dict(recon=3, block=(4, 8, 8)),
+                                 dict(refine=(((0, 0, 0), (1, 1, 1)), ((1, 0, 0), (1, 1, 1)))),
+                                 dict(refine=tuple(((0, 0, 0), (1, 1, 1)) for _ in range(9)))])
 def test_refined_configuration_errors_without_gpu(bad):
     # each case is valid without refinement and invalid with it (odd block,
-    # FOFC, box outside the root grid, block below twice the ghost depth)
+    # FOFC, box outside the root grid, block below twice the ghost depth, an
+    # empty box among several, more than 8 boxes)
     from paper_2409_16053_amd import hy
     from paper_2409_16053_amd import problems as P
     pb = P.uniform(n=(32, 24, 16), rho=1.0, v=(0, 0, 0), p=1.0, bc=P.PERIODIC)

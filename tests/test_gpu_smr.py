@@ -227,3 +227,64 @@ def test_random_refined_configurations(hy, seed):
         rm = _rel(Um, ref["U"])
         print(f"[{label}] mixed rel L1 vs FP64 reference {rm:.3e}", flush=True)
         assert rm <= 1e-5
+
+
+# ------------------------------------------------------------ several boxes
+CHECKER = tuple(((x, y, z), (x + 1, y + 1, z + 1)) for x in range(4) for y in range(2) for z in range(2)
+                if (x + y + z) % 2 == 0)
+
+
+def _several(boxes, recon, rk, seed=17, bc=P.PERIODIC):
+    from smr_cases import smooth
+    bcs = ((bc, bc),) * 3
+    make = lambda s: smooth((32 * s, 16 * s, 16 * s), bcs, seed, (8, 8, 8), recon=recon, rk=rk)
+    return _refined(make, boxes)
+
+
+def _gate(pb, steps):
+    from smr_cases import one_ulp_sensitivity
+    return max(1e-12, 100 * one_ulp_sensitivity(oracle.advance, pb, steps))
+
+
+@pytest.mark.parametrize("boxes,recon,rk,bc", [
+    (CHECKER, P.PLM, 2, P.PERIODIC),
+    ((((0, 0, 0), (2, 1, 1)), ((1, 1, 0), (2, 2, 2)), ((3, 0, 1), (4, 2, 2))), P.PPM4, 3, P.OUTFLOW),
+    ((((0, 0, 0), (2, 2, 1)), ((1, 0, 0), (3, 2, 1)), ((2, 1, 1), (4, 2, 2))), P.WENOZ, 3, P.PERIODIC),
+    (CHECKER, P.PPMX, 4, P.OUTFLOW)])
+def test_several_boxes_parity(hy, boxes, recon, rk, bc):
+    # refined regions that are not one box: a checkerboard of refined roots
+    # (a level change on every face of every leaf), an L with a separate
+    # block, overlapping boxes; FP64 gated at 1e-12 or 100x the reference
+    # solver's own one-ulp sensitivity, mixed precision at 1e-5
+    pb = _several(boxes, recon, rk, bc=bc)
+    lv = hy.leaves(pb)
+    assert np.array_equal(lv, oracle.smr_leaves(pb))
+    gate = _gate(pb, 4)
+    ref = oracle.advance(pb, 4)
+    U, q = _run(hy, pb, 4)
+    r = _rel(U, ref["U"])
+    print(f"[several boxes {len(boxes)} recon {recon} rk {rk} bc {bc}] leaves {len(lv)} "
+          f"(fine {int((lv[:, 0] == 1).sum())}) FP64 rel L1 {r:.3e} gate {gate:.1e}", flush=True)
+    assert r <= gate
+    assert abs(q["dt"] / ref["dt"] - 1) <= max(1e-11, gate)
+    Um, _ = _run(hy, pb.with_(precision=P.MIXED), 4)
+    assert _rel(Um, ref["U"]) <= 1e-5
+
+
+def test_boxes_tiling_a_box_equal_that_box_bitwise_on_gpu(hy):
+    a = _run(hy, _several(((0, 0, 0), (3, 2, 1)), P.PPM4, 2), 3)
+    b = _run(hy, _several((((0, 0, 0), (2, 1, 1)), ((2, 0, 0), (3, 2, 1)), ((0, 1, 0), (2, 2, 1))),
+                          P.PPM4, 2), 3)
+    assert np.array_equal(a[0], b[0]) and a[1]["dt"] == b[1]["dt"]
+
+
+def test_several_boxes_conserve_and_tile_shapes_bitwise(hy):
+    pb = _several(CHECKER, P.WENOZ, 3)
+    lv = hy.leaves(pb)
+    outs = [_run(hy, pb, 3, variant=v, kc=kc)[0] for v in range(len(hy.variants())) for kc in (8, 3)]
+    for U in outs[1:]:
+        assert np.array_equal(U, outs[0])
+    vol = np.where(lv[:, 0] == 0, 1.0, 0.125)
+    tot = lambda U: np.einsum("q,qv->v", vol, U.reshape(U.shape[0], 5, -1).sum(-1))
+    a = np.einsum("q,qv->v", vol, np.abs(pb.U).reshape(pb.U.shape[0], 5, -1).sum(-1))
+    assert np.all(np.abs(tot(outs[0]) - tot(pb.U)) <= 1e-13 * a)

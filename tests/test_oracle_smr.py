@@ -150,8 +150,16 @@ def _rep_numpy(pb, lv, U):
     return R0, R1
 
 
+CHECKER = tuple(((x, y, z), (x + 1, y + 1, z + 1)) for x in range(4) for y in range(2) for z in range(2)
+                if (x + y + z) % 2 == 0)[:8]  # 8 roots, every other one: level changes on every face
+
+
 @pytest.mark.parametrize("n,block,box", [((32, 16, 24), (8, 8, 8), ((0, 0, 1), (2, 1, 2))),
-                                         ((32, 24, 24), (8, 6, 12), ((1, 1, 0), (3, 3, 1)))])
+                                         ((32, 24, 24), (8, 6, 12), ((1, 1, 0), (3, 3, 1))),
+                                         ((32, 16, 16), (8, 8, 8), CHECKER),
+                                         ((32, 24, 24), (8, 6, 12), (((0, 0, 0), (2, 1, 1)),
+                                                                     ((1, 1, 0), (2, 4, 1)),
+                                                                     ((3, 2, 1), (4, 4, 2))))])
 def test_face_ghosts_match_independent_restriction_and_prolongation(oracle_lib, n, block, box):
     pb = P.uniform(n=n, rho=1.0, v=(0, 0, 0), p=1.0, bc=P.PERIODIC)
     pb = pb.with_(block=block, recon=P.PPM4, refine=box)
@@ -186,7 +194,7 @@ def _global_to_leaves(O, pb):
 def test_empty_refinement_equals_uniform_bitwise(oracle_lib, recon, rk):
     pb = P.turbulence(N=32, seed=7, kmax=6).with_(block=(16, 8, 16), recon=recon, rk=rk)
     ref = oracle_lib.advance(pb, 4)
-    pr = pb.with_(refine=((0, 0, 0), (0, 0, 0)))
+    pr = pb.with_(refine=())  # the refined-mesh path with no box refined
     UL, lv = _global_to_leaves(oracle_lib, pr)
     r = oracle_lib.advance(pr.with_(U=UL), 4)
     assert np.array_equal(r["U"], P.to_leaves(ref["U"], None, lv, pb.block))
@@ -204,6 +212,60 @@ def test_full_refinement_equals_uniform_fine_grid_bitwise(oracle_lib, bc):
     r = oracle_lib.advance(pr, 5)
     assert np.array_equal(r["U"], P.to_leaves(None, ref["U"], lv, (8, 8, 8)))
     assert r["dt"] == ref["dt"]
+
+
+# ------------------------------------------------------------ several boxes
+def test_leaves_of_several_boxes_are_their_union(oracle_lib):
+    # the refined roots are the union of the boxes: overlapping and touching
+    # boxes give the same leaves as the box they tile, and a non-box union
+    # (an L and a separate block) refines exactly the roots it covers
+    pb = P.uniform(n=(32, 24, 16), rho=1.0, v=(0, 0, 0), p=1.0, bc=P.PERIODIC).with_(block=(8, 8, 8))
+    one = oracle_lib.smr_leaves(pb.with_(refine=((0, 0, 0), (3, 2, 1))))
+    split = oracle_lib.smr_leaves(pb.with_(refine=(((0, 0, 0), (2, 2, 1)), ((2, 0, 0), (3, 2, 1)))))
+    overlap = oracle_lib.smr_leaves(pb.with_(refine=(((0, 0, 0), (2, 2, 1)), ((1, 0, 0), (3, 2, 1)),
+                                                     ((0, 1, 0), (1, 2, 1)))))
+    assert np.array_equal(one, split) and np.array_equal(one, overlap)
+    boxes = (((0, 0, 0), (2, 1, 2)), ((0, 1, 0), (1, 3, 1)), ((3, 2, 1), (4, 3, 2)))
+    lv = oracle_lib.smr_leaves(pb.with_(refine=boxes))
+    want = {(x, y, z) for (lo, hi) in boxes for x in range(lo[0], hi[0]) for y in range(lo[1], hi[1])
+            for z in range(lo[2], hi[2])}
+    got = {(int(x) // 2, int(y) // 2, int(z) // 2) for L, x, y, z in lv if L == 1}
+    assert got == want and (lv[:, 0] == 1).sum() == 8 * len(want)
+    assert (lv[:, 0] == 0).sum() == 4 * 3 * 2 - len(want)
+    for bad in ((((0, 0, 0), (1, 1, 1)), ((1, 1, 1), (1, 2, 2))),   # an empty box
+                tuple(((0, 0, 0), (1, 1, 1)) for _ in range(9))):    # more than 8
+        with pytest.raises(ValueError):
+            oracle_lib.smr_leaves(pb.with_(refine=bad))
+
+
+@pytest.mark.parametrize("recon,rk", [(P.PLM, 2), (P.PPM4, 3)])
+def test_boxes_tiling_a_box_equal_that_box_bitwise(oracle_lib, recon, rk):
+    make = lambda s: P.turbulence(N=16 * s, seed=13, kmax=4).with_(block=(8, 8, 8), recon=recon, rk=rk)
+    a = oracle_lib.advance(_refined(oracle_lib, make, ((0, 0, 1), (2, 1, 2))), 3)
+    b = oracle_lib.advance(_refined(oracle_lib, make, (((0, 0, 1), (1, 1, 2)), ((1, 0, 1), (2, 1, 2)))), 3)
+    assert np.array_equal(a["U"], b["U"]) and a["dt"] == b["dt"]
+
+
+@pytest.mark.parametrize("boxes", [CHECKER, (((0, 0, 0), (2, 1, 1)), ((1, 1, 0), (2, 2, 2)),
+                                             ((3, 0, 1), (4, 2, 2)))])
+@pytest.mark.parametrize("recon,rk", [(P.PLM, 2), (P.WENOZ, 3)])
+def test_several_boxes_conserve_and_keep_uniform(oracle_lib, boxes, recon, rk):
+    from smr_cases import smooth
+    per = ((P.PERIODIC, P.PERIODIC),) * 3
+    make = lambda s: smooth((32 * s, 16 * s, 16 * s), per, 17, (8, 8, 8), recon=recon, rk=rk)
+    pr = _refined(oracle_lib, make, boxes)
+    lv = oracle_lib.smr_leaves(pr)
+    r = oracle_lib.advance(pr, 3)
+    assert r["status"] == 0
+    s0, a0 = _totals(pr, pr.U, lv)
+    s1, a1 = _totals(pr, r["U"], lv)
+    nst = {2: 2, 3: 3}[rk]
+    bound = 8 * np.finfo(float).eps * np.sqrt(pr.cells * nst * 3)
+    assert np.all(np.abs(s1 - s0) <= bound * (a0 + a1)), (s1 - s0) / (a0 + a1)
+    mk = lambda s: P.uniform(n=(32 * s, 16 * s, 16 * s), rho=1.3, v=(0.3, -0.2, 0.1), p=0.7,
+                             bc=P.PERIODIC).with_(block=(8, 8, 8), recon=recon, rk=rk)
+    pu = _refined(oracle_lib, mk, boxes)
+    assert np.array_equal(oracle_lib.advance(pu, 2)["U"], pu.U)
 
 
 # ------------------------------------------------------------ conservation
