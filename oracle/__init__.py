@@ -120,7 +120,8 @@ def _bind(L):
     L.or_smr_leaves.restype = ctypes.c_int
     L.or_smr_new_dt.argtypes = [pp, sp, dp]
     L.or_smr_new_dt.restype = ctypes.c_double
-    L.or_smr_advance.argtypes = [pp, sp, dp, ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_longlong)]
+    L.or_smr_advance.argtypes = [pp, sp, dp, ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_longlong),
+                                 ctypes.POINTER(ctypes.c_longlong)]
     L.or_smr_advance.restype = ctypes.c_int
     L.or_smr_fill_ghosts.argtypes = [pp, sp, dp, dp]
     L.or_smr_fill_ghosts.restype = ctypes.c_int
@@ -240,8 +241,9 @@ class Oracle:
         if pb.refine is not None:  # statically refined mesh, leaf-major U
             S = smr_params(pb)
             st = self._L.or_smr_advance(ctypes.byref(P), ctypes.byref(S), _dp(U), int(nsteps),
-                                        ctypes.byref(tt), ctypes.byref(dd), ctypes.byref(fh))
-            return dict(U=U, t=tt.value, dt=dd.value, floor_hits=fh.value, fofc_cells=0,
+                                        ctypes.byref(tt), ctypes.byref(dd), ctypes.byref(fh),
+                                        ctypes.byref(fc))
+            return dict(U=U, t=tt.value, dt=dd.value, floor_hits=fh.value, fofc_cells=fc.value,
                         status=st)
         st = self._L.or_advance(ctypes.byref(P), _dp(U), int(nsteps), ctypes.byref(tt),
                                 ctypes.byref(dd), ctypes.byref(fh), ctypes.byref(fc))

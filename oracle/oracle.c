@@ -1129,12 +1129,87 @@ static void smr_stage(const smr_mesh* m, work* w, rk_coef k, const double* U0, c
   }
 }
 
+/* The leaf at the same level across face (d, side) of leaf q, or -1 when the
+ * region across is on the other level or beyond an outflow boundary. */
+static int smr_same_level(const smr_mesh* m, int q, int d, int side) {
+  const int L = m->lev[q];
+  int l[3] = {m->loc[3 * q], m->loc[3 * q + 1], m->loc[3 * q + 2]};
+  const int nl = m->nr[d] << L;
+  l[d] += side ? 1 : -1;
+  if (l[d] < 0 || l[d] >= nl) {
+    if (m->p.bc[d][0] != OR_PERIODIC) return -1;
+    l[d] = (l[d] + nl) % nl;
+  }
+  const int r = (l[0] >> L) + m->nr[0] * ((l[1] >> L) + m->nr[1] * (l[2] >> L));
+  if (m->rref[r] != L) return -1;
+  return L == 0 ? m->rleaf[r] : m->rleaf[r] + (l[0] & 1) + 2 * (l[1] & 1) + 4 * (l[2] & 1);
+}
+
+/* First-order flux correction on a refined mesh (Sec. 3 FOFC with the
+ * level-boundary flux correction of Sec. 2), after the stage's provisional
+ * update Uout: every face of a cell (any leaf) whose updated density or
+ * pressure is not positive takes the LLF flux of the first-order states at
+ * the leaf's level (the cell and, across the face, the neighbour cell or the
+ * ghost value there); a face shared with a same-level neighbour leaf is
+ * replaced in both leaves. Then the coarse faces next to finer leaves take
+ * the mean of the 4 fine fluxes again, as they stand after the replacement
+ * (at a level change the fine side's fluxes rule, also for a corrected
+ * coarse cell), and the stage is re-evaluated. Returns the flagged cells. */
+static long long smr_fofc(const smr_mesh* m, work* w, rk_coef k, const double* U0, const double* Ust,
+                          double h, double* Uout) {
+  long long flagged = 0;
+  for (int q = 0; q < m->nleaf; ++q) {
+    const or_params pl = smr_leaf_params(m, q);
+    const double* Uq = Uout + (size_t)q * m->bs;
+    for (int kk = 0; kk < m->b[2]; ++kk)
+      for (int j = 0; j < m->b[1]; ++j)
+        for (int i = 0; i < m->b[0]; ++i) {
+          const size_t c = smr_cell(m, i, j, kk);
+          const double r = Uq[c], mx = Uq[m->vs + c], my = Uq[2 * m->vs + c];
+          const double mz = Uq[3 * m->vs + c], e = Uq[4 * m->vs + c];
+          const double pr = (m->p.gamma - 1.0) * (e - 0.5 * (mx * mx + my * my + mz * mz) / r);
+          if (r > 0.0 && pr > 0.0) continue;
+          ++flagged;
+          for (int d = 0; d < 3; ++d) {
+            const int di = d == 0, dj = d == 1, dk = d == 2;
+            for (int side = 0; side < 2; ++side) {
+              const int li = i + di * (side - 1), lj = j + dj * (side - 1), lk = kk + dk * (side - 1);
+              double wl[5], wr[5], f[5];
+              for (int v = 0; v < 5; ++v) {
+                wl[v] = w[q].W[at(&w[q].G, v, li, lj, lk)];
+                wr[v] = w[q].W[at(&w[q].G, v, li + di, lj + dj, lk + dk)];
+              }
+              face_flux(&pl, d, wl, wr, f, 1);
+              int fc[3] = {i + di * side, j + dj * side, kk + dk * side};
+              for (int v = 0; v < 5; ++v) *smr_face(m, &w[q], d, v, fc[0], fc[1], fc[2]) = f[v];
+              if (fc[d] == 0 || fc[d] == m->b[d]) {
+                const int qn = smr_same_level(m, q, d, fc[d] == m->b[d]);
+                if (qn >= 0) {
+                  fc[d] = fc[d] == 0 ? m->b[d] : 0;
+                  for (int v = 0; v < 5; ++v) *smr_face(m, &w[qn], d, v, fc[0], fc[1], fc[2]) = f[v];
+                }
+              }
+            }
+          }
+        }
+  }
+  if (flagged) {
+    smr_correct_fluxes(m, w);
+    for (int q = 0; q < m->nleaf; ++q) {
+      const or_params pl = smr_leaf_params(m, q);
+      flux_divergence(&pl, &w[q]);
+    }
+    smr_stage(m, w, k, U0, Ust, h, Uout);
+  }
+  return flagged;
+}
+
 /* On any return, smr_close(m, *w) releases what was allocated. */
 static int smr_open(smr_mesh* m, work** w, const or_params* p, const or_smr* s) {
   *w = NULL;
   memset(m, 0, sizeof *m);
   if (!p || !s) return OR_ERR_ARG;
-  if (p->recon < OR_PLM || p->recon > OR_PPMX || p->rk < 1 || p->rk > 4 || p->fofc) return OR_ERR_ARG;
+  if (p->recon < OR_PLM || p->recon > OR_PPMX || p->rk < 1 || p->rk > 4) return OR_ERR_ARG;
   int st = smr_init(m, p, s);
   if (st != OR_OK) return st;
   *w = calloc((size_t)m->nleaf, sizeof(work));
@@ -1184,10 +1259,11 @@ double or_smr_new_dt(const or_params* p, const or_smr* s, const double* U) {
 }
 
 /* Advance the leaf-major state by nsteps SSP-RK steps (the stage sequence of
- * or_advance; every stage's L comes from smr_divergence). FOFC is not
- * combined with refinement here. */
+ * or_advance; every stage's L comes from smr_divergence; with p->fofc each
+ * stage is followed by smr_fofc). *fofc_cells (may be NULL) accumulates the
+ * flagged cells. */
 int or_smr_advance(const or_params* p, const or_smr* s, double* U, int nsteps, double* t,
-                   double* dt, long long* floor_hits) {
+                   double* dt, long long* floor_hits, long long* fofc_cells) {
   if (!U || !t || !dt || nsteps < 0) return OR_ERR_ARG;
   smr_mesh m;
   work* w;
@@ -1202,7 +1278,7 @@ int or_smr_advance(const or_params* p, const or_smr* s, double* U, int nsteps, d
     return OR_ERR_NOMEM;
   }
   int status = OR_OK;
-  long long hits = 0;
+  long long hits = 0, fofc = 0;
   for (int n = 0; n < nsteps; ++n) {
     const double h = *dt;
     const double* S = U;
@@ -1213,12 +1289,11 @@ int or_smr_advance(const or_params* p, const or_smr* s, double* U, int nsteps, d
       hits += smr_divergence(&m, w, S, &bad);
       if (bad) status = OR_ERR_STATE;
       double* out = (stage & 1) ? U1 : U2;
-      if (p->rk == 4) {
-        smr_stage(&m, w, stage < 10 ? RK4_STAGE : RK4_LAST, Q2, S, h, out);
-        if (stage == 5) rk4_mix(Q2, out, nt);
-      } else {
-        smr_stage(&m, w, rk_stage(p->rk, stage), U, S, h, out);
-      }
+      const rk_coef kc = p->rk == 4 ? (stage < 10 ? RK4_STAGE : RK4_LAST) : rk_stage(p->rk, stage);
+      const double* U0 = p->rk == 4 ? Q2 : U;
+      smr_stage(&m, w, kc, U0, S, h, out);
+      if (p->fofc) fofc += smr_fofc(&m, w, kc, U0, S, h, out);
+      if (p->rk == 4 && stage == 5) rk4_mix(Q2, out, nt);
       S = out;
     }
     memcpy(U, S, nt * sizeof(double));
@@ -1226,6 +1301,7 @@ int or_smr_advance(const or_params* p, const or_smr* s, double* U, int nsteps, d
     *dt = or_smr_new_dt(p, s, U);
   }
   if (floor_hits) *floor_hits += hits;
+  if (fofc_cells) *fofc_cells += fofc;
   free(U1); free(U2); free(Q2);
   smr_close(&m, w);
   return status;

@@ -18,6 +18,11 @@ replaced by the fine fluxes).
 * A smooth wave crossing the refinement boundary keeps second-order
   convergence and stays no worse than the coarse uniform mesh; a Sod shock
   crossing it keeps its star states.
+* First-order flux correction (Sec. 3) on a refined mesh: with nothing (or
+  everything) refined it equals the uniform solver's FOFC bitwise, also where
+  it fires; on flows that stay positive it changes no bit; on hypersonic
+  turbulence with a refined box it fires on both levels, keeps the state
+  positive and conserves to roundoff.
 """
 import numpy as np
 import pytest
@@ -57,18 +62,13 @@ def test_leaves_tile_the_domain_once(oracle_lib):
 
 
 @pytest.mark.parametrize("bad", [dict(n=(30, 16, 16), block=(5, 8, 8)), dict(block=(2, 8, 8)),
-                                 dict(refine=((0, 0, 0), (5, 1, 1))), dict(fofc=1)])
+                                 dict(refine=((0, 0, 0), (5, 1, 1)))])
 def test_bad_refined_mesh_is_rejected(oracle_lib, bad):
     pb = P.uniform(n=(24, 16, 16), rho=1.0, v=(0, 0, 0), p=1.0, bc=P.PERIODIC)
     pb = pb.with_(block=(8, 8, 8), refine=((0, 0, 0), (1, 1, 1)))
     pb = pb.with_(**bad)
-    if "fofc" in bad:
-        U = np.ones((len(oracle_lib.smr_leaves(pb)), 5, 8, 8, 8))
-        U[:, 4] = 2.0
-        assert oracle_lib.advance(pb, 1, U=U, dt=1e-3)["status"] == oracle_lib.ERR_ARG
-    else:
-        with pytest.raises(ValueError):
-            oracle_lib.smr_leaves(pb)
+    with pytest.raises(ValueError):
+        oracle_lib.smr_leaves(pb)
 
 
 # ------------------------------------------------------------------ ghosts
@@ -430,3 +430,75 @@ def test_random_refined_seed1_ppmx_is_ill_conditioned(oracle_lib):
     for recon in (P.PLM, P.PPM4):
         pb = random_refined(1, oracle_lib.smr_leaves, recon=recon)
         assert one_ulp_sensitivity(oracle_lib.advance, pb, 4) < 1e-14
+
+
+# ---------------------------------------------------- first-order flux correction
+def _mach20(s, recon=P.PLM, rk=2, seed=5):
+    return P.turbulence(N=16 * s, seed=seed, kmax=6, mach=20).with_(block=(8, 8, 8), recon=recon, rk=rk)
+
+
+@pytest.mark.parametrize("recon,rk", [(P.PLM, 2), (P.PPM4, 3), (P.WENOZ, 4)])
+def test_fofc_empty_refinement_equals_uniform_bitwise(oracle_lib, recon, rk):
+    # blocks of 8^3 on a periodic 16^3 mesh: every replaced face on a block
+    # edge has its twin in the neighbour leaf (or, across the periodic
+    # boundary, in the same leaf), and both must change
+    pb = _mach20(1, recon, rk).with_(fofc=1)
+    ref = oracle_lib.advance(pb, 6)
+    assert ref["fofc_cells"] > 0
+    pr = pb.with_(refine=())
+    UL, lv = _global_to_leaves(oracle_lib, pr)
+    r = oracle_lib.advance(pr.with_(U=UL), 6)
+    assert r["fofc_cells"] == ref["fofc_cells"]
+    assert np.array_equal(r["U"], P.to_leaves(ref["U"], None, lv, pb.block))
+    assert r["dt"] == ref["dt"]
+
+
+def test_fofc_full_refinement_equals_uniform_fine_grid_bitwise(oracle_lib):
+    make = lambda s: _mach20(s).with_(fofc=1)
+    ref = oracle_lib.advance(make(2), 4)
+    assert ref["fofc_cells"] > 0
+    pr = _refined(oracle_lib, make, ((0, 0, 0), (2, 2, 2)))
+    lv = oracle_lib.smr_leaves(pr)
+    r = oracle_lib.advance(pr, 4)
+    assert r["fofc_cells"] == ref["fofc_cells"]
+    assert np.array_equal(r["U"], P.to_leaves(None, ref["U"], lv, (8, 8, 8)))
+    assert r["dt"] == ref["dt"]
+
+
+@pytest.mark.parametrize("recon", [P.PLM, P.PPM4])
+def test_fofc_refined_inactive_on_positive_flows(oracle_lib, recon):
+    make = lambda s: P.turbulence(N=16 * s, seed=9, kmax=4).with_(block=(8, 8, 8), recon=recon, rk=2)
+    pr = _refined(oracle_lib, make, ((1, 0, 0), (2, 2, 1)))
+    a = oracle_lib.advance(pr, 4)
+    b = oracle_lib.advance(pr.with_(fofc=1), 4)
+    assert b["fofc_cells"] == 0
+    assert np.array_equal(a["U"], b["U"]) and a["dt"] == b["dt"]
+
+
+def _cell_pressure(U, g):
+    return (g - 1) * (U[:, 4] - 0.5 * (U[:, 1] ** 2 + U[:, 2] ** 2 + U[:, 3] ** 2) / U[:, 0])
+
+
+@pytest.mark.parametrize("recon,rk", [(P.PLM, 2), (P.PPM4, 3)])
+def test_fofc_refined_hypersonic_turbulence(oracle_lib, recon, rk):
+    g = 5.0 / 3.0
+    make = lambda s: _mach20(s, recon, rk)
+    pr = _refined(oracle_lib, make, ((0, 0, 0), (1, 2, 1)))
+    lv = oracle_lib.smr_leaves(pr)
+    plain = oracle_lib.advance(pr, 20)
+    fixed = oracle_lib.advance(pr.with_(fofc=1), 20)
+    assert plain["floor_hits"] > 0 and _cell_pressure(plain["U"], g).min() < 0
+    assert fixed["fofc_cells"] > 0
+    assert fixed["floor_hits"] * 100 < plain["floor_hits"]
+    pf = _cell_pressure(fixed["U"], g)
+    assert pf.min() > 0 and fixed["U"][:, 0].min() > 0
+    # FOFC changed the result on fine and on coarse leaves
+    diff = np.abs(fixed["U"] - plain["U"]).reshape(len(lv), -1).max(axis=1)
+    assert (diff[lv[:, 0] == 0] > 0).any() and (diff[lv[:, 0] == 1] > 0).any()
+    # conservative: replaced faces change in both leaves, and coarse faces
+    # next to fine leaves take the fine fluxes after the replacement
+    s0, a0 = _totals(pr, pr.U, lv)
+    s1, a1 = _totals(pr, fixed["U"], lv)
+    nst = {2: 2, 3: 3}[rk]
+    bound = 8 * np.finfo(float).eps * np.sqrt(pr.cells * nst * 20 * 2)
+    assert np.all(np.abs(s1 - s0) <= bound * (a0 + a1)), (s1 - s0) / (a0 + a1)
