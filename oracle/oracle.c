@@ -1100,8 +1100,9 @@ static void smr_correct_fluxes(const smr_mesh* m, work* w) {
 }
 
 /* L for every leaf of the leaf-major state S: ghost fill, fluxes, flux
- * correction, divergence (into w[q].L). */
-static long long smr_divergence(const smr_mesh* m, work* w, const double* S, int* bad) {
+ * correction (when `correct`; else each leaf keeps its own fluxes on every
+ * face), divergence (into w[q].L). */
+static long long smr_divergence(const smr_mesh* m, work* w, const double* S, int correct, int* bad) {
   long long hits = 0;
   int anybad = 0;
   for (int q = 0; q < m->nleaf; ++q) {
@@ -1111,7 +1112,7 @@ static long long smr_divergence(const smr_mesh* m, work* w, const double* S, int
     hits += prims_and_fluxes(&pl, &w[q], &b);
     anybad |= b;
   }
-  smr_correct_fluxes(m, w);
+  if (correct) smr_correct_fluxes(m, w);
   for (int q = 0; q < m->nleaf; ++q) {
     const or_params pl = smr_leaf_params(m, q);
     flux_divergence(&pl, &w[q]);
@@ -1145,20 +1146,25 @@ static int smr_same_level(const smr_mesh* m, int q, int d, int side) {
   return L == 0 ? m->rleaf[r] : m->rleaf[r] + (l[0] & 1) + 2 * (l[1] & 1) + 4 * (l[2] & 1);
 }
 
-/* First-order flux correction on a refined mesh (Sec. 3 FOFC with the
- * level-boundary flux correction of Sec. 2), after the stage's provisional
- * update Uout: every face of a cell (any leaf) whose updated density or
- * pressure is not positive takes the LLF flux of the first-order states at
- * the leaf's level (the cell and, across the face, the neighbour cell or the
- * ghost value there); a face shared with a same-level neighbour leaf is
- * replaced in both leaves. Then the coarse faces next to finer leaves take
- * the mean of the 4 fine fluxes again, as they stand after the replacement
- * (at a level change the fine side's fluxes rule, also for a corrected
- * coarse cell), and the stage is re-evaluated. Returns the flagged cells. */
-static long long smr_fofc(const smr_mesh* m, work* w, rk_coef k, const double* U0, const double* Ust,
-                          double h, double* Uout) {
+/* FOFC on the leaves of one level: the provisional update of every leaf of
+ * the level from its fluxes as they stand (into Uout), then every face of a
+ * cell whose provisional density or pressure is not positive takes the LLF
+ * flux of the first-order states at the leaf's level (the cell and, across
+ * the face, the neighbour cell or the ghost value there); a face shared with a
+ * same-level neighbour leaf is replaced in both leaves. Returns the flagged
+ * cells. */
+static long long smr_fofc_level(const smr_mesh* m, work* w, rk_coef k, const double* U0,
+                                const double* Ust, double h, double* Uout, int level) {
+  for (int q = 0; q < m->nleaf; ++q) {
+    if (m->lev[q] != level) continue;
+    const or_params pl = smr_leaf_params(m, q);
+    const size_t o = (size_t)q * m->bs;
+    flux_divergence(&pl, &w[q]);
+    stage_formula(&pl, &w[q], k, U0 + o, Ust + o, h, Uout + o);
+  }
   long long flagged = 0;
   for (int q = 0; q < m->nleaf; ++q) {
+    if (m->lev[q] != level) continue;
     const or_params pl = smr_leaf_params(m, q);
     const double* Uq = Uout + (size_t)q * m->bs;
     for (int kk = 0; kk < m->b[2]; ++kk)
@@ -1193,14 +1199,28 @@ static long long smr_fofc(const smr_mesh* m, work* w, rk_coef k, const double* U
           }
         }
   }
-  if (flagged) {
-    smr_correct_fluxes(m, w);
-    for (int q = 0; q < m->nleaf; ++q) {
-      const or_params pl = smr_leaf_params(m, q);
-      flux_divergence(&pl, &w[q]);
-    }
-    smr_stage(m, w, k, U0, Ust, h, Uout);
+  return flagged;
+}
+
+/* First-order flux correction on a refined mesh (Sec. 3 FOFC with the
+ * level-boundary flux correction of Sec. 2), finest level first; w holds
+ * every leaf's own fluxes. FOFC on the fine leaves; the coarse faces next to
+ * finer leaves take the mean of the 4 fine fluxes as they stand after it;
+ * FOFC on the coarse leaves, whose provisional update thus already has the
+ * fine side's fluxes on level faces; the level faces once more take the fine
+ * mean (the fine side's fluxes rule there, also for a corrected coarse cell);
+ * the stage from the final fluxes into Uout. Returns the flagged cells. */
+static long long smr_fofc(const smr_mesh* m, work* w, rk_coef k, const double* U0, const double* Ust,
+                          double h, double* Uout) {
+  long long flagged = smr_fofc_level(m, w, k, U0, Ust, h, Uout, 1);
+  smr_correct_fluxes(m, w);
+  flagged += smr_fofc_level(m, w, k, U0, Ust, h, Uout, 0);
+  smr_correct_fluxes(m, w);
+  for (int q = 0; q < m->nleaf; ++q) {
+    const or_params pl = smr_leaf_params(m, q);
+    flux_divergence(&pl, &w[q]);
   }
+  smr_stage(m, w, k, U0, Ust, h, Uout);
   return flagged;
 }
 
@@ -1259,9 +1279,9 @@ double or_smr_new_dt(const or_params* p, const or_smr* s, const double* U) {
 }
 
 /* Advance the leaf-major state by nsteps SSP-RK steps (the stage sequence of
- * or_advance; every stage's L comes from smr_divergence; with p->fofc each
- * stage is followed by smr_fofc). *fofc_cells (may be NULL) accumulates the
- * flagged cells. */
+ * or_advance; every stage's L comes from smr_divergence, with p->fofc
+ * without the level correction, which smr_fofc then applies). *fofc_cells
+ * (may be NULL) accumulates the flagged cells. */
 int or_smr_advance(const or_params* p, const or_smr* s, double* U, int nsteps, double* t,
                    double* dt, long long* floor_hits, long long* fofc_cells) {
   if (!U || !t || !dt || nsteps < 0) return OR_ERR_ARG;
@@ -1286,13 +1306,15 @@ int or_smr_advance(const or_params* p, const or_smr* s, double* U, int nsteps, d
     if (p->rk == 4) memcpy(Q2, U, nt * sizeof(double));
     for (int stage = 1; stage <= nst; ++stage) {
       int bad = 0;
-      hits += smr_divergence(&m, w, S, &bad);
+      hits += smr_divergence(&m, w, S, !p->fofc, &bad);
       if (bad) status = OR_ERR_STATE;
       double* out = (stage & 1) ? U1 : U2;
       const rk_coef kc = p->rk == 4 ? (stage < 10 ? RK4_STAGE : RK4_LAST) : rk_stage(p->rk, stage);
       const double* U0 = p->rk == 4 ? Q2 : U;
-      smr_stage(&m, w, kc, U0, S, h, out);
-      if (p->fofc) fofc += smr_fofc(&m, w, kc, U0, S, h, out);
+      if (p->fofc)
+        fofc += smr_fofc(&m, w, kc, U0, S, h, out);
+      else
+        smr_stage(&m, w, kc, U0, S, h, out);
       if (p->rk == 4 && stage == 5) rk4_mix(Q2, out, nt);
       S = out;
     }
@@ -1328,7 +1350,7 @@ int or_smr_divergence(const or_params* p, const or_smr* s, const double* U, doub
   int st = smr_open(&m, &w, p, s);
   if (st != OR_OK) { smr_close(&m, w); return st; }
   int bad = 0;
-  const long long h = smr_divergence(&m, w, U, &bad);
+  const long long h = smr_divergence(&m, w, U, 1, &bad);
   for (int q = 0; q < m.nleaf; ++q) memcpy(Lout + (size_t)q * m.bs, w[q].L, m.bs * sizeof(double));
   if (floor_hits) *floor_hits = h;
   smr_close(&m, w);

@@ -76,8 +76,11 @@ MUTANTS = [
     ("smr_fine_face_side", "lf[d] = side ? 0 : m->b[d];", "lf[d] = side ? m->b[d] : 0;"),
     ("smr_fofc_twin_dropped", "for (int v = 0; v < 5; ++v) *smr_face(m, &w[qn], d, v, fc[0], fc[1], fc[2]) = f[v];",
      "(void)qn;"),
-    ("smr_fofc_level_faces_not_recorrected", "  if (flagged) {\n    smr_correct_fluxes(m, w);",
-     "  if (flagged) {"),
+    ("smr_fofc_level_faces_not_corrected", "  long long flagged = smr_fofc_level(m, w, k, U0, Ust, h, Uout, 1);\n  smr_correct_fluxes(m, w);",
+     "  long long flagged = smr_fofc_level(m, w, k, U0, Ust, h, Uout, 1);"),
+    ("smr_fofc_coarse_level_first",
+     "smr_fofc_level(m, w, k, U0, Ust, h, Uout, 1);\n  smr_correct_fluxes(m, w);\n  flagged += smr_fofc_level(m, w, k, U0, Ust, h, Uout, 0);",
+     "smr_fofc_level(m, w, k, U0, Ust, h, Uout, 0);\n  smr_correct_fluxes(m, w);\n  flagged += smr_fofc_level(m, w, k, U0, Ust, h, Uout, 1);"),
     ("smr_fine_cell_width", "pl.dx[d] = m->lev[q] ? 0.5 * m->p.dx[d] : m->p.dx[d];", "pl.dx[d] = m->p.dx[d];"),
 ]
 
@@ -133,6 +136,7 @@ def _fast_pins(O):
     yield lambda: smr.test_full_refinement_equals_uniform_fine_grid_bitwise(O, P.PERIODIC)
     yield lambda: smr.test_fofc_empty_refinement_equals_uniform_bitwise(O, P.PLM, 2)
     yield lambda: smr.test_fofc_refined_hypersonic_turbulence(O, P.PLM, 2)
+    yield lambda: smr.test_fofc_refined_hypersonic_turbulence(O, P.PPM4, 3)
 
 
 def test_unplanted_build_passes_fast_pins(tmp_path):

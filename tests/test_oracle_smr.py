@@ -18,11 +18,14 @@ replaced by the fine fluxes).
 * A smooth wave crossing the refinement boundary keeps second-order
   convergence and stays no worse than the coarse uniform mesh; a Sod shock
   crossing it keeps its star states.
-* First-order flux correction (Sec. 3) on a refined mesh: with nothing (or
-  everything) refined it equals the uniform solver's FOFC bitwise, also where
-  it fires; on flows that stay positive it changes no bit; on hypersonic
-  turbulence with a refined box it fires on both levels, keeps the state
-  positive and conserves to roundoff.
+* First-order flux correction (Sec. 3) on a refined mesh, finest level
+  first (the coarse cells are tested with the fine side's final fluxes on
+  level faces): with nothing (or everything) refined it equals the uniform
+  solver's FOFC bitwise, also where it fires; on flows that stay positive it
+  changes no bit; on hypersonic turbulence with a refined box it keeps the
+  state positive (also with PPM4, where testing coarse cells before the level
+  correction leaves negative pressures next to level faces) and conserves to
+  roundoff.
 """
 import numpy as np
 import pytest
