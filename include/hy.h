@@ -81,7 +81,12 @@ enum { HY_FP64 = 0, HY_MIXED = 1 };
  *              a cell whose updated density or pressure is not positive has
  *              the fluxes on all its faces replaced by LLF fluxes of the
  *              first-order states and its stage update recomputed; 0: off.
- *              Adds 1 byte per cell to the workspace.
+ *              Adds 1 byte per (leaf) cell to the workspace. On a refined
+ *              mesh the finest level goes first: its flagged cells' faces
+ *              change (also in a same-level neighbour leaf), then a coarse
+ *              cell is tested with the fine side's fluxes, as they now
+ *              stand, on its level faces, and a flagged coarse cell keeps
+ *              them there (LLF on its other faces).
  *  rk          order of the low-storage SSP Runge-Kutta integrator (Sec. 3):
  *              1 (forward Euler), 2 (SSPRK(2,2)), 3 (SSPRK(3,3)) or 4
  *              (the ten-stage SSPRK(10,4) of Ketcheson); 0 selects 2. RK3
@@ -98,8 +103,7 @@ enum { HY_FP64 = 0, HY_MIXED = 1 };
  *              non-empty and inside the root grid; boxes may overlap or
  *              touch (two levels keep face neighbours within one level of
  *              each other for any union). With refinement,
- *              block[] must be even and >= twice the ghost depth, and fofc
- *              must be 0. Ghost cells across a level change hold the coarse
+ *              block[] must be even and >= twice the ghost depth. Ghost cells across a level change hold the coarse
  *              mean of the 8 fine cells (restriction) or, on the fine side,
  *              the coarse value plus a quarter of the minmod-limited coarse
  *              slope per axis towards the fine cell (prolongation); the flux
@@ -135,7 +139,7 @@ int32_t hy_leaves(const hy_config* cfg, int32_t* out);
  * locality", with no stored ghost cells): two FP64 state registers of
  * 5 x cells doubles each (the step-start state and the RK stage state; three
  * with rk = 3 or 4), a 1024-byte header, and with fofc one byte of flag per
- * cell. With refinement each register also holds one extra block per leaf
+ * cell (per leaf cell with refinement). With refinement each register also holds one extra block per leaf
  * face that meets a different level (its ghost slab), and the workspace holds
  * the leaf, root and face tables.
  * Returns 0 for an invalid configuration (message in hy_last_error). */

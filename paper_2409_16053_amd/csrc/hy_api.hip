@@ -115,7 +115,6 @@ bool validate(const hy_config* c, std::string& msg) {
     return false;
   }
   if (has_refine(c)) {
-    if (c->fofc) { msg = "fofc cannot be combined with mesh refinement"; return false; }
     for (int d = 0; d < 3; ++d) {
       if ((c->block[d] & 1) || c->block[d] < 2 * ng) {
         msg = "with refinement, block must be even and >= twice the ghost depth";
@@ -219,7 +218,14 @@ size_t reg_bytes(const hy_config* c) {
   return align256((size_t)register_blocks(c) * vs * 5 * sizeof(double));
 }
 
-// Refinement tables in the workspace: leaf, slab, root and coarse-face tables.
+// Largest MeshBlock face (cells).
+int max_face(const hy_config* c) {
+  return std::max(c->block[1] * c->block[2], std::max(c->block[0] * c->block[2], c->block[0] * c->block[1]));
+}
+
+// Refinement tables in the workspace: leaf, slab, root and coarse-face
+// tables, and with FOFC the saved step-start values of the level-0 cells on
+// level faces (per coarse face, the largest block face x 5 doubles).
 size_t smr_bytes(const hy_config* c, const SmrLayout* L) {
   if (!has_refine(c)) return 0;
   SmrLayout own;
@@ -227,12 +233,22 @@ size_t smr_bytes(const hy_config* c, const SmrLayout* L) {
     build_smr(c, own);
     L = &own;
   }
+  const size_t save = c->fofc ? align256((size_t)L->ncf * max_face(c) * 5 * sizeof(double)) : 0;
   return align256(L->binfo.size() * 4) + align256(L->vinfo.size() * 4 + 4) +
-         align256(L->rinfo.size() * 4) + align256(L->cfinfo.size() * 4 + 4);
+         align256(L->rinfo.size() * 4) + align256(L->cfinfo.size() * 4 + 4) + save;
 }
 
+// One FOFC flag byte per leaf cell (the ghost slabs have none).
 size_t flag_bytes(const hy_config* c) {
-  return c->fofc ? align256((size_t)c->n[0] * c->n[1] * c->n[2] * sizeof(uint8_t)) : 0;
+  if (!c->fofc) return 0;
+  const size_t cells = (size_t)c->block[0] * c->block[1] * c->block[2];
+  int64_t leaves = register_blocks(c);
+  if (has_refine(c)) {
+    SmrLayout L;
+    build_smr(c, L);
+    leaves = L.nleaf;
+  }
+  return align256((size_t)leaves * cells * sizeof(uint8_t));
 }
 
 // Tuned launch shapes per (block size, recon, precision).
@@ -464,20 +480,35 @@ hy_status run_batch(hy_problem* const* ps, const int32_t* nsteps, int32_t n, hip
         for (int q : act)  // ghost slabs across level changes, from this stage's source
           if (ps[q]->hp.nvirt > 0) HY_HIP(launch_smr_ghost(ps[q]->dp, stage, ps[q]->ng, ps[q]->hp.nvirt,
                                                           ps[q]->cfg.block, s));
+        for (int q : act)  // FOFC on a refined mesh, a stage that updates U in place
+          if (ps[q]->hp.ncf > 0 && (flags & 1) && ps[q]->cfg.fofc && ps[q]->hp.rk[stage - 1].dst == ps[q]->hp.U)
+            HY_HIP(launch_smr_save(ps[q]->dp, ps[q]->hp.ncf, ps[q]->cfg.block, s));
         for (int kind = 1; kind <= 2; ++kind) {
           st = launch_group(ps, by_kind[kind - 1], pl, stage, kind, step_of, flags, s);
           if (st != HY_OK) return st;
         }
-        if (flags & 1) {  // FOFC belongs to counted (real) stages only
+        // FOFC belongs to counted (real) stages only. On a refined mesh with
+        // FOFC, the level-0 cells on level faces are finished (and tested)
+        // by k_smr_cell before the correction pass; without FOFC, the coarse
+        // faces next to finer leaves take the fine fluxes after the stage.
+        for (int q : act)
+          if (ps[q]->hp.ncf > 0 && (flags & 1) && ps[q]->cfg.fofc) {
+            const hy_problem* pq = ps[q];
+            const uint32_t seq = (uint32_t)(pq->hp.nstages * step_of[q] + stage - 1);
+            HY_HIP(launch_smr_cell(pl.recon, pl.prec, pq->dp, stage, (int)(step_of[q] & 1), seq, pq->hp.ncf,
+                                   pq->cfg.block, s));
+          }
+        if (flags & 1) {
           st = launch_fix(ps, act, pl, stage, step_of, s);
           if (st != HY_OK) return st;
         }
-        for (int q : act)  // coarse faces next to finer leaves take the fine fluxes
+        for (int q : act)
           if (ps[q]->hp.ncf > 0) {
             const hy_problem* pq = ps[q];
             const int last = stage == pq->hp.nstages;
             const int parity = (int)(step_of[q] & 1);
-            HY_HIP(launch_smr_flux(pl.recon, pl.prec, pq->dp, stage, parity, pq->hp.ncf, pq->cfg.block, s));
+            if (!((flags & 1) && pq->cfg.fofc))
+              HY_HIP(launch_smr_flux(pl.recon, pl.prec, pq->dp, stage, parity, pq->hp.ncf, pq->cfg.block, s));
             if (last) HY_HIP(launch_smr_dt(pq->dp, pq->hp.nblocks, pq->cfg.block, parity ^ 1, s));
           }
         st = launch_combines(ps, act, stage, step_of, s);
@@ -648,6 +679,9 @@ hy_status build_problem(const hy_config* cfg, char* ws, size_t ws_bytes, int dev
     h.rinfo = (const int32_t*)t;
     t += align256(L->rinfo.size() * 4);
     h.cfinfo = (const int32_t*)t;
+    t += align256(L->cfinfo.size() * 4 + 4);
+    h.cfarea = max_face(cfg);
+    h.cfsave = cfg->fofc ? (double*)t : nullptr;
     h.nvirt = L->nvirt;
     h.ncf = L->ncf;
     for (int d = 0; d < 3; ++d) h.nroot[d] = L->nr[d];

@@ -59,6 +59,10 @@ struct DevProblem {
   const int32_t* cfinfo;     // per coarse face next to finer leaves 2: leaf, face
   int32_t nvirt, ncf;
   int32_t nroot[3];          // root blocks per axis
+  int32_t cfarea;            // cells per slot row of cfsave (largest block face)
+  double* cfsave;            // FOFC on a refined mesh: per coarse face row,
+                             // cfarea x 5 step-start values of its level-face
+                             // cells, saved before a stage that updates U in place
 };
 
 constexpr int kLeafInts = 12;  // level, neighbour per face (6), x, y, z at its level, 2 unused

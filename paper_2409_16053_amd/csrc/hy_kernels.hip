@@ -567,6 +567,29 @@ __device__ __forceinline__ bool smr_cf_leaf(const Geo& g, int nblocks) {
                         g.nb[3] >= nblocks || g.nb[4] >= nblocks || g.nb[5] >= nblocks);
 }
 
+// Bit 2 d + side set when that face of cell (i,j,k) of a level-0 leaf is a
+// level face: the cell lies on the block face and finer leaves are across
+// (a ghost slab stands in for them).
+__device__ __forceinline__ int level_faces(const Geo& g, int nblocks, int i, int j, int k) {
+  int b = 0;
+  if (i == 0 && g.nb[0] >= nblocks) b |= 1;
+  if (i == g.bx - 1 && g.nb[1] >= nblocks) b |= 2;
+  if (j == 0 && g.nb[2] >= nblocks) b |= 4;
+  if (j == g.by - 1 && g.nb[3] >= nblocks) b |= 8;
+  if (k == 0 && g.nb[4] >= nblocks) b |= 16;
+  if (k == g.bz - 1 && g.nb[5] >= nblocks) b |= 32;
+  return b;
+}
+
+// FOFC flag of the cell (i,j,k) in block-local coordinates (ghost rule of
+// ghost_local); a cell across a level change (in a ghost slab) counts as not
+// flagged: FOFC replaces fluxes within one level only.
+__device__ __forceinline__ bool flag_at(const DevProblem& P, const Geo& g, int i, int j, int k) {
+  int mb;
+  const int64_t l = ghost_local(g, i, j, k, mb);
+  return mb < P.nblocks && P.flags[(int64_t)mb * g.vstride + l] != 0;
+}
+
 // -------------------------------------------------------------- the stage
 // A pointer that is the same in every lane, moved to scalar registers. The
 // compiler does not prove the stage's register pointers uniform (they come
@@ -1102,6 +1125,60 @@ __device__ void face_llf(const Geo& geo, const Floors& fl, const Gas<T>& gas,
   out[0] = g[0]; out[n] = g[1]; out[t1] = g[2]; out[t2] = g[3]; out[4] = g[4];
 }
 
+// One of the 4 fine fluxes (e: child offset along t1 + 2 x along t2) through
+// face (d, side) of level-0 leaf q at the face cell (a1, a2) along the
+// tangential axes t1 < t2, formed by the fine leaf across exactly as its
+// stage kernel forms it; with `use_flags`, the LLF flux instead when the fine
+// cell next to the face is flagged (FOFC on the fine level).
+template <int RECON, typename T>
+__device__ void fine_face(const DevProblem& P, const Floors& fl, const Gas<T>& gas,
+                          const double* __restrict__ S, int q, int d, int side, int a1, int a2,
+                          int e, bool use_flags, double out[5]) {
+  const int bd[3] = {P.bx, P.by, P.bz};
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+  const int32_t* bq = P.binfo + (int64_t)q * kLeafInts;
+  const int n1 = 2 * P.nroot[d] * bd[d];
+  int g3[3], lf[3];
+  g3[d] = side ? 2 * (bq[7 + d] + 1) * bd[d] : 2 * bq[7 + d] * bd[d] - 1;
+  g3[d] = (g3[d] + n1) % n1;
+  g3[t1] = 2 * (bq[7 + t1] * bd[t1] + a1) + (e & 1);
+  g3[t2] = 2 * (bq[7 + t2] * bd[t2] + a2) + (e >> 1);
+  const int lx = g3[0] / bd[0], ly = g3[1] / bd[1], lz = g3[2] / bd[2];
+  const int r = (lx >> 1) + P.nroot[0] * ((ly >> 1) + P.nroot[1] * (lz >> 1));
+  const int qf = P.rinfo[2 * r + 1] + (lx & 1) + 2 * (ly & 1) + 4 * (lz & 1);
+  lf[0] = g3[0] - lx * bd[0];
+  lf[1] = g3[1] - ly * bd[1];
+  lf[2] = g3[2] - lz * bd[2];
+  // face_pair's cell index is the face's upper cell: the fine leaf's first
+  // cell when the coarse face is an upper one, one past its last otherwise
+  const int inner = side ? 0 : bd[d] - 1;
+  lf[d] = side ? 0 : bd[d];
+  Geo g;
+  geo_init(g, P, qf);
+  T fho[5], flf[5];
+  face_pair<RECON, T>(g, fl, gas, S, d, lf[0], lf[1], lf[2], fho, flf);
+  bool llf_here = false;
+  if (use_flags) {
+    int c3[3] = {lf[0], lf[1], lf[2]};
+    c3[d] = inner;
+    llf_here = P.flags[(int64_t)qf * P.vstride + ((int64_t)c3[2] * P.by + c3[1]) * P.bx + c3[0]] != 0;
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) out[v] = llf_here ? (double)flf[v] : (double)fho[v];
+}
+
+// Mean of the 4 fine fluxes through that face, summed in pairs.
+template <int RECON, typename T>
+__device__ void fine_face_mean(const DevProblem& P, const Floors& fl, const Gas<T>& gas,
+                               const double* __restrict__ S, int q, int d, int side, int a1, int a2,
+                               bool use_flags, double out[5]) {
+  double f[4][5];
+#pragma unroll 1
+  for (int e = 0; e < 4; ++e) fine_face<RECON, T>(P, fl, gas, S, q, d, side, a1, a2, e, use_flags, f[e]);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) out[v] = ((f[0][v] + f[1][v]) + (f[2][v] + f[3][v])) * 0.25;
+}
+
 constexpr int kFixPlanes = 4;  // z-planes of one MeshBlock per workgroup pass
 
 // Replace, for every cell flagged in this stage, the fluxes on all its faces by
@@ -1127,12 +1204,14 @@ __global__ void __launch_bounds__(256) k_fofc_fix(const FixArgs a) {
   const Floors fl{P.rho_floor, P.p_floor / gm1};
   const double dt = P.cfl * __longlong_as_double((long long)P.dtmin[E.parity]);
   const double cst = rs.c * dt;
-  const double id[3] = {1.0 / P.dx[0], 1.0 / P.dx[1], 1.0 / P.dx[2]};
   const int slabs = (P.bz + kFixPlanes - 1) / kFixPlanes;
   for (int w = blockIdx.x; w < P.nblocks * slabs; w += gridDim.x) {
     const int m = w / slabs, k0 = (w - m * slabs) * kFixPlanes;
     Geo geo;
     geo_init(geo, P, m);
+    const double isc = geo.lev ? 2.0 : 1.0;  // a level-1 leaf has half the root widths
+    const double id[3] = {(1.0 / P.dx[0]) * isc, (1.0 / P.dx[1]) * isc, (1.0 / P.dx[2]) * isc};
+    const bool coarse_cf = P.binfo && smr_cf_leaf(geo, P.nblocks);
     const int k1 = min(k0 + kFixPlanes, geo.bz);
     const int64_t plane = (int64_t)geo.bx * geo.by;
     for (int64_t r = (int64_t)k0 * plane + threadIdx.x; r < (int64_t)k1 * plane; r += blockDim.x) {
@@ -1141,25 +1220,38 @@ __global__ void __launch_bounds__(256) k_fofc_fix(const FixArgs a) {
       const int j = rem / geo.bx, i = rem - j * geo.bx;
       const bool me = P.flags[(int64_t)m * geo.vstride + r] != 0;
       bool nb[6];
-      nb[0] = P.flags[ghost_cell(geo, i - 1, j, k)] != 0;
-      nb[1] = P.flags[ghost_cell(geo, i + 1, j, k)] != 0;
-      nb[2] = P.flags[ghost_cell(geo, i, j - 1, k)] != 0;
-      nb[3] = P.flags[ghost_cell(geo, i, j + 1, k)] != 0;
-      nb[4] = P.flags[ghost_cell(geo, i, j, k - 1)] != 0;
-      nb[5] = P.flags[ghost_cell(geo, i, j, k + 1)] != 0;
+      nb[0] = flag_at(P, geo, i - 1, j, k);
+      nb[1] = flag_at(P, geo, i + 1, j, k);
+      nb[2] = flag_at(P, geo, i, j - 1, k);
+      nb[3] = flag_at(P, geo, i, j + 1, k);
+      nb[4] = flag_at(P, geo, i, j, k - 1);
+      nb[5] = flag_at(P, geo, i, j, k + 1);
       if (!(me || nb[0] || nb[1] || nb[2] || nb[3] || nb[4] || nb[5])) continue;
       const int64_t off = (int64_t)m * geo.bstride + r;
       if (me) {
         // the stage formula with first-order LLF fluxes on every face,
-        // divergence summed in x, y, z order as in the stage kernel
+        // divergence summed in x, y, z order as in the stage kernel; on a
+        // level face of a level-0 cell the fine side's fluxes (after FOFC on
+        // the fine level) stay
+        const int lvf = coarse_cf ? level_faces(geo, P.nblocks, i, j, k) : 0;
+        const int c3[3] = {i, j, k};
         double l[5];
         for (int d = 0; d < 3; ++d) {
-          T flo[5], fhi[5];
-          face_llf<T>(geo, fl, gas, S, d, i, j, k, flo);
-          face_llf<T>(geo, fl, gas, S, d, i + (d == 0), j + (d == 1), k + (d == 2), fhi);
+          double fs[2][5];
+          for (int s2 = 0; s2 < 2; ++s2) {
+            if ((lvf >> (2 * d + s2)) & 1) {
+              fine_face_mean<RECON, T>(P, fl, gas, S, m, d, s2, c3[d == 0 ? 1 : 0], c3[d == 2 ? 1 : 2], true,
+                                       fs[s2]);
+            } else {
+              T g[5];
+              face_llf<T>(geo, fl, gas, S, d, i + s2 * (d == 0), j + s2 * (d == 1), k + s2 * (d == 2), g);
+#pragma unroll
+              for (int v = 0; v < 5; ++v) fs[s2][v] = (double)g[v];
+            }
+          }
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            const double df = ((double)fhi[v] - (double)flo[v]) * id[d];
+            const double df = (fs[1][v] - fs[0][v]) * id[d];
             l[v] = d == 0 ? -df : l[v] - df;
           }
         }
@@ -1211,6 +1303,11 @@ __global__ void __launch_bounds__(256) k_fofc_dt(const FixArgs a) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x) {
     const int64_t m = c / P.vstride, rr = c - m * P.vstride;
+    if (P.binfo) {  // a level-0 leaf next to finer ones: k_smr_dt, after the flux correction
+      Geo g;
+      geo_init(g, P, (int)m);
+      if (smr_cf_leaf(g, P.nblocks)) continue;
+    }
     double u[5], dxb[3];
     load5c(Un, m * P.bstride + rr, P.vstride, u);
     block_dx(P, m, dxb);
@@ -1434,8 +1531,6 @@ __global__ void __launch_bounds__(256) k_smr_flux(const DevProblem* __restrict__
   const double idc = 1.0 / P.dx[d];  // the coarse leaf is on level 0
   const int bd[3] = {P.bx, P.by, P.bz};
   const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-  const int32_t* bq = P.binfo + (int64_t)q * kLeafInts;
-  const int n1 = 2 * P.nroot[d] * bd[d];
   // five threads per face cell: h = 0 the coarse flux, h = 1..4 the fine
   // ones (more threads in flight than one thread doing all five)
   __shared__ double sFl[kSmrCells][5][5];
@@ -1446,33 +1541,23 @@ __global__ void __launch_bounds__(256) k_smr_flux(const DevProblem* __restrict__
     const bool valid = cs < kSmrCells && c < area;
     const int a2 = valid ? c / bd[t1] : 0, a1 = valid ? c - a2 * bd[t1] : 0;
     if (valid) {
-      Geo g;
-      int lf[3];
+      double fo[5];
       if (h == 0) {
+        Geo g;
+        int lf[3];
         geo_init(g, P, q);
         lf[d] = side ? bd[d] : 0;  // face_pair's cell index: the face's upper cell
         lf[t1] = a1;
         lf[t2] = a2;
-      } else {
-        const int k4 = h - 1;
-        int g3[3];
-        g3[d] = side ? 2 * (bq[7 + d] + 1) * bd[d] : 2 * bq[7 + d] * bd[d] - 1;
-        g3[d] = (g3[d] + n1) % n1;
-        g3[t1] = 2 * (bq[7 + t1] * bd[t1] + a1) + (k4 & 1);
-        g3[t2] = 2 * (bq[7 + t2] * bd[t2] + a2) + (k4 >> 1);
-        const int lx = g3[0] / bd[0], ly = g3[1] / bd[1], lz = g3[2] / bd[2];
-        const int r = (lx >> 1) + P.nroot[0] * ((ly >> 1) + P.nroot[1] * (lz >> 1));
-        const int qf = P.rinfo[2 * r + 1] + (lx & 1) + 2 * (ly & 1) + 4 * (lz & 1);
-        lf[0] = g3[0] - lx * bd[0];
-        lf[1] = g3[1] - ly * bd[1];
-        lf[2] = g3[2] - lz * bd[2];
-        lf[d] = side ? 0 : bd[d];
-        geo_init(g, P, qf);
-      }
-      T fo[5], unused[5];
-      face_pair<RECON, T>(g, fl, gas, S, d, lf[0], lf[1], lf[2], fo, unused);
+        T fho[5], unused[5];
+        face_pair<RECON, T>(g, fl, gas, S, d, lf[0], lf[1], lf[2], fho, unused);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sFl[cs][h][v] = (double)fo[v];
+        for (int v = 0; v < 5; ++v) fo[v] = (double)fho[v];
+      } else {
+        fine_face<RECON, T>(P, fl, gas, S, q, d, side, a1, a2, h - 1, false, fo);
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sFl[cs][h][v] = fo[v];
     }
     __syncthreads();
     if (valid && h == 0) {
@@ -1490,6 +1575,124 @@ __global__ void __launch_bounds__(256) k_smr_flux(const DevProblem* __restrict__
       }
     }
     __syncthreads();  // sFl is reused by the next group
+  }
+}
+
+// The level-0 cells on level faces with FOFC on (Sec. 3 FOFC with the Sec. 2
+// flux correction, finest level first). Cell c of grid row e (coarse face
+// (q, f) next to finer leaves) is the face cell (a1, a2) along the tangential
+// axes; a cell on several level faces belongs to the row of its lowest face
+// index, so each is handled once.
+__device__ __forceinline__ bool cf_cell(const DevProblem& P, const Geo& geo, int f, int c, int cc[3]) {
+  const int d = f >> 1, side = f & 1;
+  const int bd[3] = {P.bx, P.by, P.bz};
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+  cc[t2] = c / bd[t1];
+  cc[t1] = c - cc[t2] * bd[t1];
+  cc[d] = side ? bd[d] - 1 : 0;
+  return (level_faces(geo, P.nblocks, cc[0], cc[1], cc[2]) & ((1 << f) - 1)) == 0;
+}
+
+// Before a stage that updates U in place: keep the step-start values of the
+// level-0 level-face cells (the stage kernel may overwrite them before
+// k_smr_cell has decided whether FOFC recomputes them from scratch).
+__global__ void __launch_bounds__(256) k_smr_save(const DevProblem* __restrict__ Pp) {
+  const DevProblem& P = *Pp;
+  const int e = blockIdx.y;
+  const int q = P.cfinfo[2 * e], f = P.cfinfo[2 * e + 1];
+  const int d = f >> 1;
+  const int area = (d == 0 ? P.by : P.bx) * (d == 2 ? P.by : P.bz);
+  Geo geo;
+  geo_init(geo, P, q);
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < area; c += gridDim.x * blockDim.x) {
+    int cc[3];
+    if (!cf_cell(P, geo, f, c, cc)) continue;
+    const int64_t off = (int64_t)q * P.bstride + ((int64_t)cc[2] * P.by + cc[1]) * P.bx + cc[0];
+    double* sv = P.cfsave + ((int64_t)e * P.cfarea + c) * 5;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sv[v] = P.U[off + v * P.vstride];
+  }
+}
+
+// The stage update of those cells computed whole from the stage's source:
+// on a level face the mean of the 4 fine fluxes as FOFC on the fine level
+// left them (each the LLF flux when the fine cell behind it is flagged), on
+// every other face the cell's own high-order flux. The stage kernel tested
+// them with their own coarse fluxes; this test replaces that one (flag and
+// counter adjusted). A result that is positive is stored; a flagged cell is
+// left to k_fofc_fix, with its step-start value put back into U when the
+// stage updates U in place (the stage kernel may have stored over it).
+template <int RECON, typename T>
+__global__ void __launch_bounds__(256) k_smr_cell(const DevProblem* __restrict__ Pp, int stage, int parity,
+                                                  unsigned seq) {
+  const DevProblem& P = *Pp;
+  const int e = blockIdx.y;
+  const int q = P.cfinfo[2 * e], f = P.cfinfo[2 * e + 1];
+  const int d = f >> 1;
+  const RkStage& rs = P.rk[stage - 1];
+  const double* __restrict__ S = rs.src;
+  double* Out = rs.dst;
+  const bool inplace = Out == P.U;
+  const double gamma = P.gamma, gm1 = gamma - 1.0;
+  const Gas<T> gas{T(gamma), T(gm1), T((gamma + 1.0) / (2.0 * gamma))};
+  const Floors fl{P.rho_floor, P.p_floor / gm1};
+  const double dt = P.cfl * __longlong_as_double((long long)P.dtmin[parity]);
+  const double id[3] = {1.0 / P.dx[0], 1.0 / P.dx[1], 1.0 / P.dx[2]};  // level-0 widths
+  const int area = (d == 0 ? P.by : P.bx) * (d == 2 ? P.by : P.bz);
+  Geo geo;
+  geo_init(geo, P, q);
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < area; c += gridDim.x * blockDim.x) {
+    int cc[3];
+    if (!cf_cell(P, geo, f, c, cc)) continue;
+    const int lvf = level_faces(geo, P.nblocks, cc[0], cc[1], cc[2]);
+    double l[5];
+    for (int d2 = 0; d2 < 3; ++d2) {
+      const int u1 = d2 == 0 ? 1 : 0, u2 = d2 == 2 ? 1 : 2;
+      double fs[2][5];
+      for (int s2 = 0; s2 < 2; ++s2) {
+        if ((lvf >> (2 * d2 + s2)) & 1) {
+          fine_face_mean<RECON, T>(P, fl, gas, S, q, d2, s2, cc[u1], cc[u2], true, fs[s2]);
+        } else {
+          T fho[5], unused[5];
+          face_pair<RECON, T>(geo, fl, gas, S, d2, cc[0] + s2 * (d2 == 0), cc[1] + s2 * (d2 == 1),
+                              cc[2] + s2 * (d2 == 2), fho, unused);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) fs[s2][v] = (double)fho[v];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double df = (fs[1][v] - fs[0][v]) * id[d2];
+        l[v] = d2 == 0 ? -df : l[v] - df;
+      }
+    }
+    const int64_t r = ((int64_t)cc[2] * P.by + cc[1]) * P.bx + cc[0];
+    const int64_t off = (int64_t)q * P.bstride + r;
+    const double* sv = P.cfsave + ((int64_t)e * P.cfarea + c) * 5;
+    double us[5], u0[5], unew[5];
+    load5c(S, off, P.vstride, us);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u0[v] = inplace ? sv[v] : P.U[off + v * P.vstride];
+    if (rs.a == 0.0) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) unew[v] = us[v] + (rs.c * dt) * l[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) unew[v] = (rs.a * u0[v] + rs.b * us[v]) + (rs.c * dt) * l[v];
+    }
+    const double ke2 = (unew[1] * unew[1] + unew[2] * unew[2]) + unew[3] * unew[3];
+    const double pn = gm1 * (unew[4] - (0.5 * ke2) * rcp(unew[0]));
+    const bool flag = !(unew[0] > 0.0) || !(pn > 0.0);
+    const bool was = P.flags[(int64_t)q * P.vstride + r] != 0;
+    P.flags[(int64_t)q * P.vstride + r] = flag ? 1 : 0;
+    if (flag != was) atomicAdd(P.fofc_cnt + (seq & 1), flag ? 1ull : ~0ull);  // +1 or -1
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      if (!flag)
+        Out[off + v * P.vstride] = unew[v];
+      else if (inplace)
+        Out[off + v * P.vstride] = u0[v];
+    }
   }
 }
 
@@ -1746,6 +1949,27 @@ hipError_t launch_smr_dt(const DevProblem* p, int nleaf, const int32_t block[3],
   const int cells = block[0] * block[1] * block[2];
   const int gx = std::max(1, std::min((cells + 255) / 256, 64));
   hipLaunchKernelGGL(k_smr_dt, dim3(gx, nleaf), dim3(256), 0, s, p, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_smr_save(const DevProblem* p, int ncf, const int32_t block[3], hipStream_t s) {
+  const int area = std::max(block[1] * block[2], std::max(block[0] * block[2], block[0] * block[1]));
+  const int gx = std::max(1, std::min((area + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_smr_save, dim3(gx, ncf), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_smr_cell(int recon, int prec, const DevProblem* p, int stage, int parity, unsigned seq,
+                           int ncf, const int32_t block[3], hipStream_t s) {
+  using K = void (*)(const DevProblem*, int, int, unsigned);
+  static const K tab[4][2] = {{k_smr_cell<0, double>, k_smr_cell<0, float>},
+                              {k_smr_cell<1, double>, k_smr_cell<1, float>},
+                              {k_smr_cell<2, double>, k_smr_cell<2, float>},
+                              {k_smr_cell<3, double>, k_smr_cell<3, float>}};
+  if (recon < 0 || recon > 3 || prec < 0 || prec > 1) return hipErrorInvalidValue;
+  const int area = std::max(block[1] * block[2], std::max(block[0] * block[2], block[0] * block[1]));
+  const int gx = std::max(1, std::min((area + 255) / 256, 1024));
+  hipLaunchKernelGGL(tab[recon][prec], dim3(gx, ncf), dim3(256), 0, s, p, stage, parity, seq);
   return hipGetLastError();
 }
 

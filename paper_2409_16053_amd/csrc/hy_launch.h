@@ -23,6 +23,9 @@ hipError_t launch_smr_ghost(const DevProblem* p, int stage, int ng, int nvirt, c
                             hipStream_t s);
 hipError_t launch_smr_flux(int recon, int prec, const DevProblem* p, int stage, int parity, int ncf,
                            const int32_t block[3], hipStream_t s);
+hipError_t launch_smr_save(const DevProblem* p, int ncf, const int32_t block[3], hipStream_t s);
+hipError_t launch_smr_cell(int recon, int prec, const DevProblem* p, int stage, int parity, unsigned seq,
+                           int ncf, const int32_t block[3], hipStream_t s);
 hipError_t launch_smr_dt(const DevProblem* p, int nleaf, const int32_t block[3], int slot,
                          hipStream_t s);
 }  // namespace hy

@@ -107,15 +107,19 @@ def test_refined_leaves_and_workspace_without_gpu(box, periodic):
     reg = a((len(lv) + nvirt) * 8 ** 3 * 5 * 8)
     tables = a(len(lv) * 12 * 4) + a(nvirt * 2 * 4 + 4) + a(24 * 2 * 4) + a(ncf * 2 * 4 + 4)
     assert hy.workspace_bytes(pb) == 1024 + 3 * reg + tables
+    # FOFC adds one flag byte per leaf cell (none for the ghost slabs) and,
+    # per coarse face next to finer leaves, room for one block face of states
+    assert hy.workspace_bytes(pb.with_(fofc=1)) == (1024 + 3 * reg + a(len(lv) * 8 ** 3) + tables
+                                                    + a(ncf * 64 * 5 * 8))
 
 
-@pytest.mark.parametrize("bad", [dict(block=(9, 8, 8), n=(36, 24, 16)), dict(fofc=1),
+@pytest.mark.parametrize("bad", [dict(block=(9, 8, 8), n=(36, 24, 16)),
                                  dict(refine=((0, 0, 0), (5, 1, 1))), dict(recon=3, block=(4, 8, 8)),
                                  dict(refine=(((0, 0, 0), (1, 1, 1)), ((1, 0, 0), (1, 1, 1)))),
                                  dict(refine=tuple(((0, 0, 0), (1, 1, 1)) for _ in range(9)))])
 def test_refined_configuration_errors_without_gpu(bad):
     # each case is valid without refinement and invalid with it (odd block,
-    # FOFC, box outside the root grid, block below twice the ghost depth, an
+    # box outside the root grid, block below twice the ghost depth, an
     # empty box among several, more than 8 boxes)
     from paper_2409_16053_amd import hy
     from paper_2409_16053_amd import problems as P
