@@ -80,11 +80,16 @@ def test_refined_fofc_matches_reference(hy, recon, rk, bc, box):
 
 
 def test_refined_fofc_inactive_on_positive_flow(hy):
+    # nothing is flagged; the level-0 cells on level faces are then computed
+    # whole by k_smr_cell rather than corrected after the stage, so the two
+    # runs agree up to rounding (not bitwise, as on a uniform mesh)
     make = lambda s: P.turbulence(N=32 * s, seed=3, kmax=6).with_(block=(16, 16, 16), rk=2)
     pb = _refined(make, ((1, 0, 0), (2, 1, 2)))
     a, qa = _run(hy, pb, 6)
     b, qb = _run(hy, pb.with_(fofc=1), 6)
-    assert qb["fofc_cells"] == 0 and np.array_equal(a, b) and qa["dt"] == qb["dt"]
+    print(f"[smr fofc inactive] rel L1 {_rel(b, a):.3e}", flush=True)
+    assert qb["fofc_cells"] == 0 and qb["floor_hits"] == qa["floor_hits"]
+    assert _rel(b, a) <= 1e-14 and abs(qb["dt"] / qa["dt"] - 1) <= 1e-14
 
 
 def test_refined_fofc_tile_shapes_bitwise(hy):
