@@ -139,9 +139,11 @@ int32_t hy_leaves(const hy_config* cfg, int32_t* out);
  * locality", with no stored ghost cells): two FP64 state registers of
  * 5 x cells doubles each (the step-start state and the RK stage state; three
  * with rk = 3 or 4), a 1024-byte header, and with fofc one byte of flag per
- * cell (per leaf cell with refinement). With refinement each register also holds one extra block per leaf
- * face that meets a different level (its ghost slab), and the workspace holds
- * the leaf, root and face tables.
+ * cell (per leaf cell with refinement). With refinement each register also
+ * holds, per leaf face that meets a different level, the ghost cells there
+ * (its ghost slab: ghost depth x the largest block face cells, packed into
+ * whole blocks after the leaves), and the workspace holds the leaf, root and
+ * face tables.
  * Returns 0 for an invalid configuration (message in hy_last_error). */
 size_t hy_workspace_bytes(const hy_config* cfg);
 

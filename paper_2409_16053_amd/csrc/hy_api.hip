@@ -205,12 +205,27 @@ void build_smr(const hy_config* c, SmrLayout& L) {
   }
 }
 
-// Blocks per register: leaves plus slabs with refinement, else the root grid.
+// Ghost slabs packed into one block of a register: log2 of the count, and
+// the cells per variable of one slab (ghost depth x largest block face).
+int slab_cells(const hy_config* c) {
+  return ghost_depth(c->recon) *
+         std::max(c->block[1] * c->block[2], std::max(c->block[0] * c->block[2], c->block[0] * c->block[1]));
+}
+int slab_k2(const hy_config* c) {
+  const int64_t per = (int64_t)c->block[0] * c->block[1] * c->block[2] / slab_cells(c);
+  int k2 = 0;
+  while ((int64_t(2) << k2) <= per) ++k2;
+  return k2;
+}
+
+// Blocks per register: with refinement the leaves plus the blocks that hold
+// the packed ghost slabs, else the root grid.
 int64_t register_blocks(const hy_config* c) {
   if (!has_refine(c)) return (int64_t)(c->n[0] / c->block[0]) * (c->n[1] / c->block[1]) * (c->n[2] / c->block[2]);
   SmrLayout L;
   build_smr(c, L);
-  return (int64_t)L.nleaf + L.nvirt;
+  const int64_t per = int64_t(1) << slab_k2(c);
+  return (int64_t)L.nleaf + (L.nvirt + per - 1) / per;
 }
 
 size_t reg_bytes(const hy_config* c) {
@@ -372,10 +387,12 @@ hy_status launch_group(hy_problem* const* ps, const std::vector<int>& act, const
     StageArgs a;
     std::memset(&a, 0, sizeof a);
     int64_t tiles = 0;
+    int smr = 0;  // a refined problem in the launch: the stage kernel that knows ghost slabs
     const size_t c1 = std::min(act.size(), c0 + (size_t)kMaxBatch);
     for (size_t c = c0; c < c1; ++c) {
       const int q = act[c];
       const hy_problem* p = ps[q];
+      smr |= p->hp.binfo != nullptr;
       BatchEntry& e = a.e[a.nprob++];
       e.p = p->dp;
       e.tile0 = (int32_t)tiles;
@@ -392,7 +409,7 @@ hy_status launch_group(hy_problem* const* ps, const std::vector<int>& act, const
     if (tiles > 0x7fffffff) return fail(HY_ERR_ARG, "too many tiles in one launch");
     a.ntiles = (int32_t)tiles;
     if (tiles == 0) continue;
-    HY_HIP(launch_stage(pl.variant, pl.recon, pl.prec, kind, a, (int)tiles, s));
+    HY_HIP(launch_stage(pl.variant, pl.recon, pl.prec, kind, smr, a, (int)tiles, s));
   }
   return HY_OK;
 }
@@ -681,6 +698,8 @@ hy_status build_problem(const hy_config* cfg, char* ws, size_t ws_bytes, int dev
     h.cfinfo = (const int32_t*)t;
     t += align256(L->cfinfo.size() * 4 + 4);
     h.cfarea = max_face(cfg);
+    h.slab_k2 = slab_k2(cfg);
+    h.slab_cells = slab_cells(cfg);
     h.cfsave = cfg->fofc ? (double*)t : nullptr;
     h.nvirt = L->nvirt;
     h.ncf = L->ncf;

@@ -59,6 +59,12 @@ struct DevProblem {
   const int32_t* cfinfo;     // per coarse face next to finer leaves 2: leaf, face
   int32_t nvirt, ncf;
   int32_t nroot[3];          // root blocks per axis
+  int32_t slab_k2;           // log2 of the ghost slabs packed into one block
+  int32_t slab_cells;        // cells per variable of a packed slab (ghost depth
+                             // x largest block face); a slab's layer l along
+                             // its face normal, tangential cell (a1, a2) (axes
+                             // in x, y, z order) sits at slot * slab_cells +
+                             // (l * n2 + a2) * n1 + a1 within its block
   int32_t cfarea;            // cells per slot row of cfsave (largest block face)
   double* cfsave;            // FOFC on a refined mesh: per coarse face row,
                              // cfarea x 5 step-start values of its level-face

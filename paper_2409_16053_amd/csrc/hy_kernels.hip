@@ -374,12 +374,17 @@ struct Geo {
   int m;       // this tile's block
   int nb[6];   // neighbour block per face (-x,+x,-y,+y,-z,+z); -1 = outflow
   int lev;     // refinement level (0 without refinement)
+  int nleaf;   // blocks below this index are leaves; above, ghost slabs
   int64_t bstride, vstride;
+  int64_t sbase[6];  // per face with a ghost slab across: offset of that slab's
+                     // packed cells (variable 0) in a register
 };
 
 // UNIFORM: m is the same in every lane of the wave (the stage kernel's tile
-// block), which lets the leaf table's entries live in scalar registers.
-template <bool UNIFORM = false>
+// block), which lets the leaf table's entries live in scalar registers. SMR:
+// the mesh may be refined (false only in stage kernels launched for uniform
+// meshes alone).
+template <bool UNIFORM = false, bool SMR = true>
 __device__ __forceinline__ void geo_init(Geo& g, const DevProblem& P, int m) {
   g.bx = P.bx;
   g.by = P.by;
@@ -388,11 +393,18 @@ __device__ __forceinline__ void geo_init(Geo& g, const DevProblem& P, int m) {
   g.bstride = P.bstride;
   g.vstride = P.vstride;
   g.lev = 0;
-  if (P.binfo) {  // refined mesh: the leaf table (a slab stands in for a level change)
+  g.nleaf = P.nblocks;
+  if (SMR && P.binfo) {  // refined mesh: the leaf table (a slab stands in for a level change)
     const int32_t* b = P.binfo + (int64_t)m * kLeafInts;
     g.lev = UNIFORM ? __builtin_amdgcn_readfirstlane(b[0]) : b[0];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) g.nb[f] = UNIFORM ? __builtin_amdgcn_readfirstlane(b[1 + f]) : b[1 + f];
+    for (int f = 0; f < 6; ++f) {
+      g.nb[f] = UNIFORM ? __builtin_amdgcn_readfirstlane(b[1 + f]) : b[1 + f];
+      // slabs are packed 2^slab_k2 to a block after the leaves (DevProblem::slab_cells)
+      const int vb = g.nb[f] - P.nblocks;
+      g.sbase[f] = (int64_t)(P.nblocks + (vb >> P.slab_k2)) * P.bstride +
+                   (int64_t)(vb & ((1 << P.slab_k2) - 1)) * P.slab_cells;
+    }
     return;
   }
   const int nbx = P.nbx, nby = P.nby, nbz = P.nbz;
@@ -409,38 +421,88 @@ __device__ __forceinline__ void geo_init(Geo& g, const DevProblem& P, int m) {
 // Offset (in doubles, variable 0) of cell (i,j,k) given in this block's local
 // coordinates, of which at most one may lie outside the block by <= its size:
 // the ghost-zone rule of periodic / neighbour copies and outflow clamping.
+// Across a level change the neighbour is a ghost slab (mb_out >= nleaf),
+// whose layers next to the face are packed (DevProblem::slab_cells): then
+// mb_out * bstride + the value returned is the cell's offset. SMR = false: a
+// uniform mesh, no slabs.
+template <bool SMR = true>
 __device__ __forceinline__ int64_t ghost_local(const Geo& g, int i, int j, int k, int& mb_out) {
-  int mb = g.m;
+  int mb = g.m, f = 0;
   if (i < 0) {
-    if (g.nb[0] >= 0) { mb = g.nb[0]; i += g.bx; } else { i = 0; }
+    if (g.nb[0] >= 0) { mb = g.nb[0]; i += g.bx; f = 0; } else { i = 0; }
   } else if (i >= g.bx) {
-    if (g.nb[1] >= 0) { mb = g.nb[1]; i -= g.bx; } else { i = g.bx - 1; }
+    if (g.nb[1] >= 0) { mb = g.nb[1]; i -= g.bx; f = 1; } else { i = g.bx - 1; }
   }
   if (j < 0) {
-    if (g.nb[2] >= 0) { mb = g.nb[2]; j += g.by; } else { j = 0; }
+    if (g.nb[2] >= 0) { mb = g.nb[2]; j += g.by; f = 2; } else { j = 0; }
   } else if (j >= g.by) {
-    if (g.nb[3] >= 0) { mb = g.nb[3]; j -= g.by; } else { j = g.by - 1; }
+    if (g.nb[3] >= 0) { mb = g.nb[3]; j -= g.by; f = 3; } else { j = g.by - 1; }
   }
   if (k < 0) {
-    if (g.nb[4] >= 0) { mb = g.nb[4]; k += g.bz; } else { k = 0; }
+    if (g.nb[4] >= 0) { mb = g.nb[4]; k += g.bz; f = 4; } else { k = 0; }
   } else if (k >= g.bz) {
-    if (g.nb[5] >= 0) { mb = g.nb[5]; k -= g.bz; } else { k = g.bz - 1; }
+    if (g.nb[5] >= 0) { mb = g.nb[5]; k -= g.bz; f = 5; } else { k = g.bz - 1; }
+  }
+  if (SMR && mb >= g.nleaf) {  // the ghost slab of this block's face f
+    const int d = f >> 1;
+    const int c = d == 0 ? i : (d == 1 ? j : k);
+    const int n = d == 0 ? g.bx : (d == 1 ? g.by : g.bz);
+    const int layer = (f & 1) ? c : n - 1 - c;  // 0 next to the face
+    const int a1 = d == 0 ? j : i, a2 = d == 2 ? j : k;
+    const int n1 = d == 0 ? g.by : g.bx, n2 = d == 2 ? g.by : g.bz;
+    mb_out = mb;  // mb * bstride + the value returned is the slab cell's offset
+    return g.sbase[f] - (int64_t)mb * g.bstride + ((int64_t)layer * n2 + a2) * n1 + a1;
   }
   mb_out = mb;
   return ((int64_t)k * g.by + j) * g.bx + i;
 }
 
+template <bool SMR = true>
 __device__ __forceinline__ int64_t ghost_off(const Geo& g, int i, int j, int k) {
   int mb;
-  const int64_t l = ghost_local(g, i, j, k, mb);
+  const int64_t l = ghost_local<SMR>(g, i, j, k, mb);
   return (int64_t)mb * g.bstride + l;
 }
 
-// Cell index (block * cells per block + local) of the same ghost rule.
-__device__ __forceinline__ int64_t ghost_cell(const Geo& g, int i, int j, int k) {
-  int mb;
-  const int64_t l = ghost_local(g, i, j, k, mb);
-  return (int64_t)mb * g.vstride + l;
+// ghost_off for a cell of this block's column (i, j) at a plane k outside the
+// block (below or above it by <= bz): only the z faces are crossed, so the
+// whole choice is wave-uniform when k is.
+template <bool SMR = true>
+__device__ __forceinline__ int64_t ghost_off_z(const Geo& g, int i, int j, int k) {
+  const bool up = k >= g.bz;
+  const int nb = up ? g.nb[5] : g.nb[4];
+  if (nb < 0) return (int64_t)g.m * g.bstride + ((int64_t)(up ? g.bz - 1 : 0) * g.by + j) * g.bx + i;
+  const int kk = up ? k - g.bz : k + g.bz;
+  if (SMR && nb >= g.nleaf) {  // the ghost slab of this block's z face
+    const int layer = up ? kk : g.bz - 1 - kk;
+    return (up ? g.sbase[5] : g.sbase[4]) + ((int64_t)layer * g.by + j) * g.bx + i;
+  }
+  return (int64_t)nb * g.bstride + ((int64_t)kk * g.by + j) * g.bx + i;
+}
+
+// ghost_off for a cell of plane k (inside the block) of which i or j (not
+// both) may lie outside the block by <= its size.
+template <bool SMR = true>
+__device__ __forceinline__ int64_t ghost_off_xy(const Geo& g, int i, int j, int k) {
+  int mb = g.m, f = -1;
+  if (i < 0) {
+    if (g.nb[0] >= 0) { mb = g.nb[0]; i += g.bx; f = 0; } else { i = 0; }
+  } else if (i >= g.bx) {
+    if (g.nb[1] >= 0) { mb = g.nb[1]; i -= g.bx; f = 1; } else { i = g.bx - 1; }
+  }
+  if (j < 0) {
+    if (g.nb[2] >= 0) { mb = g.nb[2]; j += g.by; f = 2; } else { j = 0; }
+  } else if (j >= g.by) {
+    if (g.nb[3] >= 0) { mb = g.nb[3]; j -= g.by; f = 3; } else { j = g.by - 1; }
+  }
+  if (SMR && mb >= g.nleaf) {  // the ghost slab of this block's x or y face f
+    const bool x = f < 2;
+    const int c = x ? i : j, n = x ? g.bx : g.by;
+    const int layer = (f & 1) ? c : n - 1 - c;
+    const int a1 = x ? j : i, n1 = x ? g.by : g.bx;
+    return g.sbase[f] + ((int64_t)layer * g.bz + k) * n1 + a1;
+  }
+  return (int64_t)mb * g.bstride + ((int64_t)k * g.by + j) * g.bx + i;
 }
 
 __device__ __forceinline__ void load5(const double* __restrict__ base, int64_t off, int64_t vs,
@@ -610,7 +672,7 @@ __device__ __forceinline__ P* uniform_ptr(P* p) {
 // V = U + dt L(U), then U = U/2 + V/2 + dt L(V)/2; RK3 and RK4 in its
 // table). The last stage of a problem also reduces the minimum of
 // dx_d/lambda_d over its new state for the next time step.
-template <int RECON, typename T, int TX, int TY, int WPE, int STAGE>
+template <int RECON, typename T, int TX, int TY, int WPE, int STAGE, bool SMR>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_stage(const StageArgs a) {
   constexpr int NG = RECON == 0 ? 2 : 3;
@@ -651,7 +713,7 @@ k_stage(const StageArgs a) {
     const int txi = r - tyi * E.ntx;
 
     Geo geo;
-    geo_init<true>(geo, P, m);
+    geo_init<true, SMR>(geo, P, m);
     const int i0 = txi * TX, j0 = tyi * TY, k0 = tzi * E.kc;
     const int nxv = min(TX, geo.bx - i0), nyv = min(TY, geo.by - j0);
     const int kend = min(k0 + E.kc, geo.bz);
@@ -673,10 +735,10 @@ k_stage(const StageArgs a) {
     // a level-1 block has half the root widths: scaling by a power of two
     // commutes with rounding (and with the minimum of the time step), so the
     // root widths are used and the results scaled once
-    const double isc = geo.lev ? 2.0 : 1.0, dsc = geo.lev ? 0.5 : 1.0;
+    const double isc = SMR && geo.lev ? 2.0 : 1.0, dsc = SMR && geo.lev ? 0.5 : 1.0;
     // the tiles of a coarse leaf next to finer ones leave the time step to
     // k_smr_dt, which runs after the flux correction has changed the leaf
-    const bool last_dt = last && !(P.binfo && smr_cf_leaf(geo, P.nblocks));
+    const bool last_dt = last && !(SMR && P.binfo && smr_cf_leaf(geo, P.nblocks));
     const double idx = (1.0 / P.dx[0]) * isc, idy = (1.0 / P.dx[1]) * isc, idz = (1.0 / P.dx[2]) * isc;
     const bool count = (E.flags & 1) != 0;
 
@@ -697,7 +759,7 @@ k_stage(const StageArgs a) {
     const int64_t pstride = (int64_t)geo.by * geo.bx;
 
     auto col_load = [&](int k, double u[5]) {
-      const int64_t off = (k >= 0 && k < geo.bz) ? col0 + k * pstride : ghost_off(geo, gi, gj, k);
+      const int64_t off = (k >= 0 && k < geo.bz) ? col0 + k * pstride : ghost_off_z<SMR>(geo, gi, gj, k);
       load5c(Sin, off, vs, u);
     };
     auto to_prim = [&](const double u[5], T w[5], int k) {
@@ -845,7 +907,7 @@ k_stage(const StageArgs a) {
         }
         if (ok) {
           double u[5], wd[5];
-          load5c(Sin, ghost_off(geo, i0 + li, j0 + lj, k), vs, u);
+          load5c(Sin, ghost_off_xy<SMR>(geo, i0 + li, j0 + lj, k), vs, u);
           int hh = 0, bb = 0;
           c2p(fl, u, wd, hh, bb);
 #pragma unroll
@@ -1399,9 +1461,10 @@ __device__ __forceinline__ double minmod2(double a, double b) {
 constexpr int kGhostCC = 32;  // coarse cells per k_smr_ghost prolongation pass (256 threads)
 
 // Fill every ghost slab of one problem (grid row = slab) from the stage's
-// source register, all 5 variables per cell. Slab blocks follow the leaves in
-// the same register; a slab cell sits where ghost_local looks for it (the
-// neighbour block's frame), so the stage kernel reads it unchanged.
+// source register, all 5 variables per cell. The slabs are packed after the
+// leaves in the same register (DevProblem::slab_cells): layer l along the
+// face normal (0 next to the face), then the tangential axes, which is where
+// ghost_local and its variants look for them.
 __global__ void __launch_bounds__(256) k_smr_ghost(const DevProblem* __restrict__ Pp, int stage, int ng) {
   const DevProblem& P = *Pp;
   double* S = const_cast<double*>(P.rk[stage - 1].src);
@@ -1413,7 +1476,8 @@ __global__ void __launch_bounds__(256) k_smr_ghost(const DevProblem* __restrict_
   const int bd[3] = {P.bx, P.by, P.bz};
   const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
   const int nl = (P.nroot[d] * bd[d]) << lev;
-  double* slab = S + (int64_t)(P.nblocks + vb) * P.bstride;
+  double* slab = S + (int64_t)(P.nblocks + (vb >> P.slab_k2)) * P.bstride +
+                 (int64_t)(vb & ((1 << P.slab_k2) - 1)) * P.slab_cells;
   auto ghost_d = [&](int l) {  // global index along d of ghost layer l, at the slab's level
     return wrap_or_clamp(side ? b[7 + d] * bd[d] + bd[d] + l : b[7 + d] * bd[d] - 1 - l, nl, P.periodic[d]);
   };
@@ -1422,16 +1486,13 @@ __global__ void __launch_bounds__(256) k_smr_ghost(const DevProblem* __restrict_
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ng * area; c += gridDim.x * blockDim.x) {
       const int l = c / area, rem = c - l * area;
       const int a2 = rem / bd[t1], a1 = rem - a2 * bd[t1];
-      int g3[3], s3[3];
+      int g3[3];
       g3[t1] = b[7 + t1] * bd[t1] + a1;
       g3[t2] = b[7 + t2] * bd[t2] + a2;
       g3[d] = ghost_d(l);
       double u[5];
       smr_level0(P, S, g3[0], g3[1], g3[2], u);
-      s3[t1] = a1;
-      s3[t2] = a2;
-      s3[d] = side ? l : bd[d] - 1 - l;
-      double* o = slab + ((int64_t)s3[2] * P.by + s3[1]) * P.bx + s3[0];
+      double* o = slab + ((int64_t)l * bd[t2] + a2) * bd[t1] + a1;  // packed: layer, then t2, t1
 #pragma unroll
       for (int v = 0; v < 5; ++v) o[v * P.vstride] = u[v];
     }
@@ -1478,14 +1539,11 @@ __global__ void __launch_bounds__(256) k_smr_ghost(const DevProblem* __restrict_
         coarse_of(base + cs, c3, L, c1, c2);
         const int l = 2 * L + (e & 1);
         if (l < ng) {
-          int odd[3], s3[3];
+          int odd[3];
           odd[d] = ghost_d(l) & 1;
           odd[t1] = (e >> 1) & 1;  // leaf bases are even: the local parity is the global one
           odd[t2] = e >> 2;
-          s3[d] = side ? l : bd[d] - 1 - l;
-          s3[t1] = 2 * c1 + odd[t1];
-          s3[t2] = 2 * c2 + odd[t2];
-          double* o = slab + ((int64_t)s3[2] * P.by + s3[1]) * P.bx + s3[0];
+          double* o = slab + ((int64_t)l * bd[t2] + (2 * c2 + odd[t2])) * bd[t1] + (2 * c1 + odd[t1]);
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
             const double C = sv[cs][0][v];
@@ -1835,7 +1893,8 @@ __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32
 // Compiled tile shapes: TX x TY threads (a multiple of 64) and the occupancy
 // the register allocator targets (waves per SIMD; more waves hide latency
 // better but may force spills).
-#define HY_K(R, T, TX, TY, W, S) (const void*)&k_stage<R, T, TX, TY, W, S>
+#define HY_K(R, T, TX, TY, W, S) \
+  {(const void*)&k_stage<R, T, TX, TY, W, S, false>, (const void*)&k_stage<R, T, TX, TY, W, S, true>}
 #define HY_RECON_SET(R, TX, TY, W)                                                    \
   {{HY_K(R, double, TX, TY, W, 1), HY_K(R, double, TX, TY, W, 2)},                    \
    {HY_K(R, float, TX, TY, W, 1), HY_K(R, float, TX, TY, W, 2)}}
@@ -1846,7 +1905,7 @@ __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32
 
 struct StageVariant {
   int tx, ty, wpe;
-  const void* fn[4][2][2];  // [recon][precision][kind: first stage, later stage]
+  const void* fn[4][2][2][2];  // [recon][precision][kind: first, later stage][refined mesh]
 };
 
 static const StageVariant kStageVariants[] = {
@@ -1864,15 +1923,16 @@ void stage_variant_shape(int v, int* tx, int* ty) {
 int stage_variant_waves(int v) { return kStageVariants[v].wpe; }
 
 // kind 1: the first RK stage; kind 2: any later stage.
-const void* stage_kernel(int v, int recon, int prec, int kind) {
-  return kStageVariants[v].fn[recon][prec][kind - 1];
+const void* stage_kernel(int v, int recon, int prec, int kind, int smr) {
+  return kStageVariants[v].fn[recon][prec][kind - 1][smr ? 1 : 0];
 }
 
-hipError_t launch_stage(int v, int recon, int prec, int kind, const StageArgs& a, int grid,
+hipError_t launch_stage(int v, int recon, int prec, int kind, int smr, const StageArgs& a, int grid,
                         hipStream_t s) {
   const StageVariant& sv = kStageVariants[v];
   void* args[] = {(void*)&a};
-  return hipLaunchKernel(sv.fn[recon][prec][kind - 1], dim3(grid), dim3(sv.tx * sv.ty), args, 0, s);
+  return hipLaunchKernel(sv.fn[recon][prec][kind - 1][smr ? 1 : 0], dim3(grid), dim3(sv.tx * sv.ty), args,
+                         0, s);
 }
 
 hipError_t launch_fofc(int recon, int prec, const FixArgs& a, int grid_x, hipStream_t s) {

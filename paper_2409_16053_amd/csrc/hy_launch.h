@@ -6,8 +6,8 @@ namespace hy {
 int num_stage_variants();
 void stage_variant_shape(int v, int* tx, int* ty);
 int stage_variant_waves(int v);
-const void* stage_kernel(int v, int recon, int prec, int stage);
-hipError_t launch_stage(int v, int recon, int prec, int stage, const StageArgs& a, int grid,
+const void* stage_kernel(int v, int recon, int prec, int stage, int smr);
+hipError_t launch_stage(int v, int recon, int prec, int stage, int smr, const StageArgs& a, int grid,
                         hipStream_t s);
 hipError_t launch_fofc(int recon, int prec, const FixArgs& a, int grid_x, hipStream_t s);
 int fofc_grid(int nblocks, int bz);

@@ -104,7 +104,9 @@ def test_refined_leaves_and_workspace_without_gpu(box, periodic):
     assert np.array_equal(lv, oracle.smr_leaves(pb))
     nvirt, ncf = _slab_faces(lv, (4, 3, 2), periodic)
     a = lambda b: (b + 255) // 256 * 256
-    reg = a((len(lv) + nvirt) * 8 ** 3 * 5 * 8)
+    # the slabs' 2 ghost layers of a 64-cell face are packed 4 to a block
+    # (512 cells per variable / 128 per slab)
+    reg = a((len(lv) + (nvirt + 3) // 4) * 8 ** 3 * 5 * 8)
     tables = a(len(lv) * 12 * 4) + a(nvirt * 2 * 4 + 4) + a(24 * 2 * 4) + a(ncf * 2 * 4 + 4)
     assert hy.workspace_bytes(pb) == 1024 + 3 * reg + tables
     # FOFC adds one flag byte per leaf cell (none for the ghost slabs) and,
