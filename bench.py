@@ -191,11 +191,9 @@ def main():
     dom = 2 if a2 >= a1 else 1
     avg = a2 if dom == 2 else a1
     achieved = BYTES_STAGE[dom] * cells / avg / 1e9
-    traffic = None
-    if os.path.exists(COUNTERS):
-        c = json.load(open(COUNTERS))
-        if c.get("kernel_source_hash") == kernel_source_hash() and c.get("cells") == cells:
-            traffic = c.get(f"stage{dom}_hbm_bytes_per_launch")
+    launch_key = "{},{}".format(*r64["launch"])
+    counters = launch_counters(cells, launch_key)
+    traffic = counters.get(f"stage{dom}_hbm_bytes_per_launch") if counters else None
     out["roofline"] = {
         "bound": "hbm",
         "achieved": achieved,
@@ -203,7 +201,7 @@ def main():
         "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
         "traffic": traffic,
-        "kernel": "k_stage<0, double, {}, {}, {}, {}>".format(*hy.variants_full()[r64["launch"][0]], dom),
+        "kernel": "k_stage<0, double, {}, {}, {}, {}, false>".format(*hy.variants_full()[r64["launch"][0]], dom),
         "avg_launch_ms": avg * 1e3,
         "other_stage_avg_launch_ms": (a1 if dom == 2 else a2) * 1e3,
         "bytes_per_cell": BYTES_STAGE[dom],
@@ -261,7 +259,7 @@ def main():
             "value": small.cells / (t1 - t0), "unit": "cell-updates/s", "cores": 1,
             "sample": f"1 RK2 step of 128^3 turbulence (same recipe), {t1 - t0:.1f} s wall"}
 
-    valu = valu_summary(cells, a1 if dom == 1 else a2, dom)
+    valu = valu_summary(counters, cells, a1 if dom == 1 else a2, dom)
     if valu is not None:
         out["roofline"]["valu"] = valu
 
@@ -284,15 +282,24 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def valu_summary(cells, avg_s, stage):
-    """FP64 vector work of the dominant stage kernel from the committed SQ
-    counters (instructions per launch, wave-level), if they were taken on the
-    current kernel source: issued FP64 lane operations per second against the
-    chip's FP64 lane rate."""
+def launch_counters(cells, launch):
+    """The committed counter summary of the dominant stage kernels for one
+    launch shape ("variant,kc"), if it was taken on the current kernel source
+    and workload size; else None."""
     if not os.path.exists(COUNTERS):
         return None
     c = json.load(open(COUNTERS))
     if c.get("kernel_source_hash") != kernel_source_hash() or c.get("cells") != cells:
+        return None
+    return c.get("by_launch", {}).get(launch)
+
+
+def valu_summary(c, cells, avg_s, stage):
+    """FP64 vector work of the dominant stage kernel from the committed SQ
+    counters of its launch shape (instructions per launch, wave-level):
+    issued FP64 lane operations per second against the chip's FP64 lane
+    rate."""
+    if not c:
         return None
     n = c.get(f"stage{stage}_fp64_valu_insts_per_launch")
     if n is None:
