@@ -94,6 +94,8 @@ def main():
                     help="time only the statically refined workload (for profiling)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the two batch workloads (for profiling)")
+    ap.add_argument("--kh-only", action="store_true",
+                    help="time only the 512^3 PPM4 workload (for profiling)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the 256^3 FP64 (and mixed) lines")
     ap.add_argument("--serve-budget-gb", default="16,8,64",
@@ -158,6 +160,10 @@ def main():
     if args.refined_only:
         print(json.dumps({"refined": run_refined(run, hy, P, None, args.steps, cpu=not args.skip_cpu)}),
               flush=True)
+        return
+
+    if args.kh_only:
+        print(json.dumps({"kh512": run_kh512(run, P, hy, cpu=not args.skip_cpu)}), flush=True)
         return
 
     log("timing FP64")
