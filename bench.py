@@ -9,6 +9,8 @@ steps / wall seconds, state resident in HBM); the mixed-precision path is
 timed the same way and reported beside it.
 
 Prints one JSON line. Beside the headline it reports, unless switched off:
+  fofc      first-order flux correction: idle cost on the headline state, and
+            rms Mach 20 turbulence (uniform, and refined) where it fires
   kh512     the 512^3 Kelvin-Helmholtz workload (64 MeshBlocks of 128^3, PPM4,
             10 steps), FP64 and mixed
   schemes   the 256^3 workload with WENO-Z + SSP-RK3 and PPMX + SSP-RK3 (FP64
@@ -94,6 +96,9 @@ def main():
                     help="time only the statically refined workload (for profiling)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the two batch workloads (for profiling)")
+    ap.add_argument("--skip-fofc", action="store_true", help="skip the first-order flux correction lines")
+    ap.add_argument("--fofc-only", action="store_true",
+                    help="time only the first-order flux correction workloads (for profiling)")
     ap.add_argument("--kh-only", action="store_true",
                     help="time only the 512^3 PPM4 workload (for profiling)")
     ap.add_argument("--headline-only", action="store_true",
@@ -164,6 +169,10 @@ def main():
 
     if args.kh_only:
         print(json.dumps({"kh512": run_kh512(run, P, hy, cpu=not args.skip_cpu)}), flush=True)
+        return
+
+    if args.fofc_only:
+        print(json.dumps({"fofc": run_fofc(run, hy, P, args.steps, None)}), flush=True)
         return
 
     log("timing FP64")
@@ -277,6 +286,8 @@ def main():
             out["kh512"] = run_kh512(run, P, hy, cpu=not args.skip_cpu)
         if not args.skip_refined:
             out["refined"] = run_refined(run, hy, P, value, args.steps, cpu=not args.skip_cpu)
+        if not args.skip_fofc:
+            out["fofc"] = run_fofc(run, hy, P, args.steps, value)
         if not args.no_batch:
             out["batch"] = run_batch_workload(hy, P, torch)
             out["batch_small"] = run_batch_workload(hy, P, torch, seed=5, sizes=(32, 48),
@@ -369,6 +380,44 @@ def run_refined(run, hy, P, uniform_value, steps, cpu=True):
         out["cpu_baseline"] = {"value": pb.cells / (t1 - t0), "unit": "cell-updates/s",
                                "cores": oracle.get_threads(), "kind": "oracle",
                                "sample": f"1 RK2 step of the refined mesh, {t1 - t0:.1f} s wall"}
+    return out
+
+
+def run_fofc(run, hy, P, steps, uniform_value):
+    """First-order flux correction (Sec. 3) on 256^3 meshes of 64^3 blocks,
+    PLM+HLLC, SSP-RK2, FP64: the headline state with FOFC on (a flow that
+    stays positive, so the cost of FOFC when it never fires), and rms Mach 20
+    turbulence with structure down to 4 cells (k = 1..64), where the plain
+    scheme needs the floors
+    and FOFC fires, without and with FOFC, uniform and with the central 2^3
+    root blocks refined once (fine leaves injected from their parents)."""
+    out = {"steps": steps}
+    base, _ = P.workload_turbulence_256()
+    log("timing FOFC on the headline state")
+    r = run(P.FP64, prob=base.with_(fofc=1), steps=steps)
+    out["idle"] = {"workload": "the headline turbulence 256^3 (rms Mach 0.5) with FOFC on",
+                   "value": base.cells * steps / r["sec"], "unit": "cell-updates/s",
+                   "ms_per_step": 1e3 * r["sec"] / steps, "fofc_cells": r["q"]["fofc_cells"]}
+    if uniform_value:
+        out["idle"]["rate_vs_fofc_off"] = out["idle"]["value"] / uniform_value
+    log("building rms Mach 20 turbulence 256^3")
+    m20 = P.turbulence(N=256, seed=1, kmax=64, mach=20).with_(block=(64, 64, 64), recon=P.PLM)
+    for name, prob in (("mach20_off", m20), ("mach20", m20.with_(fofc=1))):
+        log(f"timing {name}")
+        r = run(P.FP64, prob=prob, steps=steps)
+        out[name] = {"value": m20.cells * steps / r["sec"], "unit": "cell-updates/s",
+                     "ms_per_step": 1e3 * r["sec"] / steps, "fofc_cells": r["q"]["fofc_cells"],
+                     "floor_hits": r["q"]["floor_hits"]}
+    out["mach20"]["workload"] = ("turbulence 256^3 periodic, k^-5/3 over k = 1..64, rms Mach 20, "
+                                 "64 MeshBlocks of 64^3, FOFC on")
+    log("timing refined rms Mach 20 with FOFC")
+    pr = P.inject_to_leaves(m20, P.REFINED_BOX_256, hy.leaves(m20.with_(refine=P.REFINED_BOX_256)))
+    r = run(P.FP64, prob=pr.with_(fofc=1), steps=steps)
+    out["mach20_refined"] = {"workload": "the rms Mach 20 state with the central 2^3 of 4^3 root blocks "
+                                         "refined once (120 leaves of 64^3), FOFC on",
+                             "value": pr.cells * steps / r["sec"], "unit": "cell-updates/s",
+                             "ms_per_step": 1e3 * r["sec"] / steps, "fofc_cells": r["q"]["fofc_cells"],
+                             "floor_hits": r["q"]["floor_hits"]}
     return out
 
 

@@ -253,17 +253,21 @@ size_t smr_bytes(const hy_config* c, const SmrLayout* L) {
          align256(L->rinfo.size() * 4) + align256(L->cfinfo.size() * 4 + 4) + save;
 }
 
-// One FOFC flag byte per leaf cell (the ghost slabs have none).
+// One FOFC flag byte per leaf cell (the ghost slabs have none), then one
+// byte per unit of kFixPlanes planes of a leaf (the correction pass's mask).
+int64_t leaf_count(const hy_config* c) {
+  if (!has_refine(c)) return register_blocks(c);
+  SmrLayout L;
+  build_smr(c, L);
+  return L.nleaf;
+}
+size_t cell_flag_bytes(const hy_config* c) {
+  return align256((size_t)leaf_count(c) * c->block[0] * c->block[1] * c->block[2]);
+}
 size_t flag_bytes(const hy_config* c) {
   if (!c->fofc) return 0;
-  const size_t cells = (size_t)c->block[0] * c->block[1] * c->block[2];
-  int64_t leaves = register_blocks(c);
-  if (has_refine(c)) {
-    SmrLayout L;
-    build_smr(c, L);
-    leaves = L.nleaf;
-  }
-  return align256((size_t)leaves * cells * sizeof(uint8_t));
+  const size_t units = (size_t)leaf_count(c) * ((c->block[2] + kFixPlanes - 1) / kFixPlanes);
+  return cell_flag_bytes(c) + align256(units);
 }
 
 // Tuned launch shapes per (block size, recon, precision).
@@ -680,6 +684,7 @@ hy_status build_problem(const hy_config* cfg, char* ws, size_t ws_bytes, int dev
   const int nreg = registers_of(cfg);
   h.W = nreg == 3 ? (double*)(p->ws + kHeaderBytes + 2 * reg_bytes(cfg)) : nullptr;
   h.flags = cfg->fofc ? (uint8_t*)(p->ws + kHeaderBytes + (size_t)nreg * reg_bytes(cfg)) : nullptr;
+  h.fixmask = cfg->fofc ? h.flags + cell_flag_bytes(cfg) : nullptr;
   h.fofc_cnt = p->dc->fofc_cnt;
   h.fofc_total = &p->dc->fofc_total;
   h.nstages = stages_of(cfg);

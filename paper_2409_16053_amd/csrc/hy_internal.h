@@ -15,6 +15,7 @@ namespace hy {
 
 constexpr int kHeaderBytes = 1024;
 constexpr int kMaxBatch = 48;   // problems per launch (kernel-argument budget)
+constexpr int kFixPlanes = 1;   // z-planes of one MeshBlock per FOFC correction unit
 constexpr int kWave = 64;       // CDNA wavefront width
 
 // One low-storage SSP-RK stage: dst = a U + b src + c dt L(src), evaluated as
@@ -45,6 +46,10 @@ struct DevProblem {
   double dx[3];
   double gamma, cfl, rho_floor, p_floor;
   uint8_t* flags;            // per-cell FOFC flag of the latest counted stage
+  uint8_t* fixmask;          // per (leaf, kFixPlanes-plane unit of it): bit 0 set if
+                             // a cell in it is flagged, bits 1-4 if a flagged cell
+                             // lies on its -x, +x, -y, +y face (set before each
+                             // correction pass)
   unsigned long long* fofc_cnt;  // [2] cells flagged in the stages of sequence parity 0/1
   unsigned long long* fofc_total;
   int32_t fofc;              // 1: first-order flux correction enabled

@@ -1241,7 +1241,35 @@ __device__ void fine_face_mean(const DevProblem& P, const Floors& fl, const Gas<
   for (int v = 0; v < 5; ++v) out[v] = ((f[0][v] + f[1][v]) + (f[2][v] + f[3][v])) * 0.25;
 }
 
-constexpr int kFixPlanes = 4;  // z-planes of one MeshBlock per workgroup pass
+// Before a correction pass: per unit of kFixPlanes planes of a leaf, whether
+// any of its cells is flagged, and whether one on each of its four side faces
+// is (so that k_fofc_fix can pass over the units with no flagged cell in them
+// or next to them). Exits at once when nothing was flagged.
+__global__ void __launch_bounds__(256) k_fofc_mark(const FixArgs a) {
+  const FixEntry E = a.e[blockIdx.y];
+  const DevProblem& P = *E.p;
+  if (P.fofc_cnt[E.seq & 1] == 0ull) return;
+  const int units = (P.bz + kFixPlanes - 1) / kFixPlanes;
+  const int64_t plane = (int64_t)P.bx * P.by;
+  __shared__ int acc;
+  for (int w = blockIdx.x; w < P.nblocks * units; w += gridDim.x) {
+    const int m = w / units, k0 = (w - m * units) * kFixPlanes;
+    const int k1 = min(k0 + kFixPlanes, P.bz);
+    const uint8_t* f = P.flags + (int64_t)m * P.vstride + k0 * plane;
+    if (threadIdx.x == 0) acc = 0;
+    __syncthreads();
+    int bits = 0;
+    for (int64_t r = threadIdx.x; r < (k1 - k0) * plane; r += blockDim.x) {
+      if (!f[r]) continue;
+      const int rem = (int)(r % plane), j = rem / P.bx, i = rem - j * P.bx;
+      bits |= 1 | (i == 0 ? 2 : 0) | (i == P.bx - 1 ? 4 : 0) | (j == 0 ? 8 : 0) | (j == P.by - 1 ? 16 : 0);
+    }
+    if (bits) atomicOr(&acc, bits);
+    __syncthreads();
+    if (threadIdx.x == 0) P.fixmask[w] = (uint8_t)acc;
+    __syncthreads();  // acc is reset for the next unit
+  }
+}
 
 // Replace, for every cell flagged in this stage, the fluxes on all its faces by
 // LLF fluxes of the first-order states. A flagged cell (whose store the stage
@@ -1268,9 +1296,21 @@ __global__ void __launch_bounds__(256) k_fofc_fix(const FixArgs a) {
   const double cst = rs.c * dt;
   const int slabs = (P.bz + kFixPlanes - 1) / kFixPlanes;
   for (int w = blockIdx.x; w < P.nblocks * slabs; w += gridDim.x) {
-    const int m = w / slabs, k0 = (w - m * slabs) * kFixPlanes;
+    const int m = w / slabs, sl = w - m * slabs, k0 = sl * kFixPlanes;
     Geo geo;
     geo_init(geo, P, m);
+    {  // a unit with no flagged cell in it or next to it changes nothing
+      bool need = (P.fixmask[w] & 1) || (sl > 0 && (P.fixmask[w - 1] & 1)) ||
+                  (sl + 1 < slabs && (P.fixmask[w + 1] & 1));
+      // x and y neighbours (same planes): a flagged cell on their face towards this unit
+      for (int f = 0; f < 4; ++f)
+        need = need || (geo.nb[f] >= 0 && geo.nb[f] < P.nblocks &&
+                        (P.fixmask[geo.nb[f] * slabs + sl] & (2 << (f ^ 1))));
+      if (sl == 0 && geo.nb[4] >= 0 && geo.nb[4] < P.nblocks)
+        need = need || (P.fixmask[geo.nb[4] * slabs + slabs - 1] & 1);
+      if (sl + 1 == slabs && geo.nb[5] >= 0 && geo.nb[5] < P.nblocks) need = need || (P.fixmask[geo.nb[5] * slabs] & 1);
+      if (!need) continue;
+    }
     const double isc = geo.lev ? 2.0 : 1.0;  // a level-1 leaf has half the root widths
     const double id[3] = {(1.0 / P.dx[0]) * isc, (1.0 / P.dx[1]) * isc, (1.0 / P.dx[2]) * isc};
     const bool coarse_cf = P.binfo && smr_cf_leaf(geo, P.nblocks);
@@ -1942,7 +1982,9 @@ hipError_t launch_fofc(int recon, int prec, const FixArgs& a, int grid_x, hipStr
       {(const void*)&k_fofc_fix<2, double>, (const void*)&k_fofc_fix<2, float>},
       {(const void*)&k_fofc_fix<3, double>, (const void*)&k_fofc_fix<3, float>}};
   void* args[] = {(void*)&a};
-  hipError_t e = hipLaunchKernel(fix[recon][prec], dim3(grid_x, a.nprob), dim3(256), args, 0, s);
+  hipError_t e = hipLaunchKernel((const void*)&k_fofc_mark, dim3(grid_x, a.nprob), dim3(256), args, 0, s);
+  if (e != hipSuccess) return e;
+  e = hipLaunchKernel(fix[recon][prec], dim3(grid_x, a.nprob), dim3(256), args, 0, s);
   if (e != hipSuccess || !a.any_last) return e;
   return hipLaunchKernel((const void*)&k_fofc_dt, dim3(grid_x, a.nprob), dim3(256), args, 0, s);
 }

@@ -109,10 +109,11 @@ def test_refined_leaves_and_workspace_without_gpu(box, periodic):
     reg = a((len(lv) + (nvirt + 3) // 4) * 8 ** 3 * 5 * 8)
     tables = a(len(lv) * 12 * 4) + a(nvirt * 2 * 4 + 4) + a(24 * 2 * 4) + a(ncf * 2 * 4 + 4)
     assert hy.workspace_bytes(pb) == 1024 + 3 * reg + tables
-    # FOFC adds one flag byte per leaf cell (none for the ghost slabs) and,
-    # per coarse face next to finer leaves, room for one block face of states
-    assert hy.workspace_bytes(pb.with_(fofc=1)) == (1024 + 3 * reg + a(len(lv) * 8 ** 3) + tables
-                                                    + a(ncf * 64 * 5 * 8))
+    # FOFC adds one flag byte per leaf cell (none for the ghost slabs) and one
+    # per plane of a leaf, and, per coarse face next to finer leaves, room for
+    # one block face of states
+    assert hy.workspace_bytes(pb.with_(fofc=1)) == (1024 + 3 * reg + a(len(lv) * 8 ** 3) + a(len(lv) * 8)
+                                                    + tables + a(ncf * 64 * 5 * 8))
 
 
 @pytest.mark.parametrize("bad", [dict(block=(9, 8, 8), n=(36, 24, 16)),

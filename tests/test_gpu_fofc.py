@@ -53,6 +53,22 @@ def test_fofc_hypersonic_turbulence_matches_reference(hy, recon):
     assert _pmin(U) > 0
 
 
+@pytest.mark.parametrize("recon,N", [(P.PLM, 32), (P.PPM4, 24)])
+def test_fofc_small_blocks_matches_reference(hy, recon, N):
+    # blocks of 8^3: a quarter of the cells lie on a block face, so flagged
+    # cells whose neighbours across the face (in another block) need the
+    # correction are common; the correction pass must find those blocks'
+    # planes from the face bits of the flagged side
+    pb = P.turbulence(N=N, seed=5, kmax=8, mach=20).with_(block=(8, 8, 8), recon=recon, fofc=1)
+    U, q = _run(hy, pb, 6)
+    ref = oracle.advance(pb, 6)
+    r = _rel(U, ref["U"])
+    print(f"[fofc 8^3 blocks recon {recon}] rel L1 {r:.3e}  cells {q['fofc_cells']}/{ref['fofc_cells']}", flush=True)
+    assert ref["fofc_cells"] > 0 and q["fofc_cells"] == ref["fofc_cells"]
+    assert q["floor_hits"] == ref["floor_hits"]
+    assert r <= 1e-12 and abs(q["dt"] / ref["dt"] - 1) <= 1e-11
+
+
 def test_fofc_inactive_on_positive_flow(hy):
     pb = P.kelvin_helmholtz(N=32, seed=6).with_(block=(16, 16, 16))
     a, qa = _run(hy, pb, 8)
