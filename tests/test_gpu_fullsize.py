@@ -12,6 +12,10 @@ times (chosen by the same whole-step autotuning on a scratch copy).
 * The refined 256^3 mesh of the benchmark (central 2^3 root blocks refined
   once): one step against the reference solver, 20 steps for the same
   properties.
+* First-order flux correction on the benchmark's rms Mach 20 turbulence
+  (256^3, structure down to 4 cells): 20 steps uniform and 2 steps with the
+  central root blocks refined, against the reference solver, corrected-cell
+  and floor counts equal.
 """
 import numpy as np
 import pytest
@@ -108,3 +112,32 @@ def test_turbulence_256_refined_full_size(hy):
     rm = _rel(Um, U)
     print(f"[refined 256 full] 20 steps: mixed vs FP64 rel L1 {rm:.3e}", flush=True)
     assert rm <= 1e-5
+
+
+def _mach20():
+    return P.turbulence(N=256, seed=1, kmax=64, mach=20).with_(block=(64, 64, 64), recon=P.PLM, fofc=1)
+
+
+def test_fofc_mach20_full_size(hy):
+    pb = _mach20()
+    U, q, launch = _run_tuned(hy, pb, 20)
+    ref = oracle.advance(pb, 20)
+    r = _rel(U, ref["U"])
+    print(f"[fofc mach20 256 full] launch {launch} rel L1 {r:.3e} cells {q['fofc_cells']}/{ref['fofc_cells']} "
+          f"floors {q['floor_hits']}/{ref['floor_hits']}", flush=True)
+    assert ref["fofc_cells"] > 0 and q["fofc_cells"] == ref["fofc_cells"]
+    assert q["floor_hits"] == ref["floor_hits"]
+    assert r <= 1e-12 and abs(q["dt"] / ref["dt"] - 1) <= 1e-11
+
+
+def test_fofc_mach20_refined_full_size(hy):
+    m20 = _mach20()
+    pb = P.inject_to_leaves(m20, P.REFINED_BOX_256, hy.leaves(m20.with_(refine=P.REFINED_BOX_256)))
+    U, q, launch = _run_tuned(hy, pb, 2)
+    ref = oracle.advance(pb, 2)
+    r = _rel(U, ref["U"])
+    print(f"[fofc mach20 refined 256 full] launch {launch} rel L1 {r:.3e} cells {q['fofc_cells']}/"
+          f"{ref['fofc_cells']} floors {q['floor_hits']}/{ref['floor_hits']}", flush=True)
+    assert ref["fofc_cells"] > 0 and q["fofc_cells"] == ref["fofc_cells"]
+    assert q["floor_hits"] == ref["floor_hits"]
+    assert r <= 1e-12 and abs(q["dt"] / ref["dt"] - 1) <= 1e-11
