@@ -1602,85 +1602,11 @@ __global__ void __launch_bounds__(256) k_smr_ghost(const DevProblem* __restrict_
   }
 }
 
-constexpr int kSmrCells = 51;  // face cells per k_smr_flux workgroup pass (5 threads each)
-
-// Flux correction along direction `dir` (Sec. 2: the flux through a coarse
-// face shared with finer blocks is the finer blocks' flux): for each coarse
-// face next to 4 fine faces (cfinfo), the coarse cell adds
-// c dt (F_coarse - mean F_fine) / dx on an upper face, the opposite on a
-// lower one, both fluxes recomputed from the stage's source exactly as the
-// stage kernel formed them. One launch per direction, so no cell is updated
-// twice within a launch.
-template <int RECON, typename T>
-__global__ void __launch_bounds__(256) k_smr_flux(const DevProblem* __restrict__ Pp, int stage, int parity,
-                                                  int dir) {
-  const DevProblem& P = *Pp;
-  const int e = blockIdx.y;
-  const int q = P.cfinfo[2 * e], f = P.cfinfo[2 * e + 1];
-  const int d = f >> 1, side = f & 1;
-  if (d != dir) return;
-  const RkStage& rs = P.rk[stage - 1];
-  const double* __restrict__ S = rs.src;
-  double* Out = rs.dst;
-  const double gamma = P.gamma, gm1 = gamma - 1.0;
-  const Gas<T> gas{T(gamma), T(gm1), T((gamma + 1.0) / (2.0 * gamma))};
-  const Floors fl{P.rho_floor, P.p_floor / gm1};
-  const double cst = rs.c * (P.cfl * __longlong_as_double((long long)P.dtmin[parity]));
-  const double idc = 1.0 / P.dx[d];  // the coarse leaf is on level 0
-  const int bd[3] = {P.bx, P.by, P.bz};
-  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-  // five threads per face cell: h = 0 the coarse flux, h = 1..4 the fine
-  // ones (more threads in flight than one thread doing all five)
-  __shared__ double sFl[kSmrCells][5][5];
-  const int cs = threadIdx.x / 5, h = threadIdx.x - 5 * cs;
-  const int area = bd[t1] * bd[t2];
-  for (int base = blockIdx.x * kSmrCells; base < area; base += gridDim.x * kSmrCells) {
-    const int c = base + cs;
-    const bool valid = cs < kSmrCells && c < area;
-    const int a2 = valid ? c / bd[t1] : 0, a1 = valid ? c - a2 * bd[t1] : 0;
-    if (valid) {
-      double fo[5];
-      if (h == 0) {
-        Geo g;
-        int lf[3];
-        geo_init(g, P, q);
-        lf[d] = side ? bd[d] : 0;  // face_pair's cell index: the face's upper cell
-        lf[t1] = a1;
-        lf[t2] = a2;
-        T fho[5], unused[5];
-        face_pair<RECON, T>(g, fl, gas, S, d, lf[0], lf[1], lf[2], fho, unused);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) fo[v] = (double)fho[v];
-      } else {
-        fine_face<RECON, T>(P, fl, gas, S, q, d, side, a1, a2, h - 1, false, fo);
-      }
-#pragma unroll
-      for (int v = 0; v < 5; ++v) sFl[cs][h][v] = fo[v];
-    }
-    __syncthreads();
-    if (valid && h == 0) {
-      int cc[3];
-      cc[d] = side ? bd[d] - 1 : 0;
-      cc[t1] = a1;
-      cc[t2] = a2;
-      const int64_t off = (int64_t)q * P.bstride + ((int64_t)cc[2] * P.by + cc[1]) * P.bx + cc[0];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const double fc = sFl[cs][0][v];
-        const double mean = ((sFl[cs][1][v] + sFl[cs][2][v]) + (sFl[cs][3][v] + sFl[cs][4][v])) * 0.25;
-        const double dl = side ? (fc - mean) * idc : (mean - fc) * idc;
-        Out[off + v * P.vstride] += cst * dl;
-      }
-    }
-    __syncthreads();  // sFl is reused by the next group
-  }
-}
-
-// The level-0 cells on level faces with FOFC on (Sec. 3 FOFC with the Sec. 2
-// flux correction, finest level first). Cell c of grid row e (coarse face
-// (q, f) next to finer leaves) is the face cell (a1, a2) along the tangential
-// axes; a cell on several level faces belongs to the row of its lowest face
-// index, so each is handled once.
+// The level-0 cells on level faces (next to finer leaves). Cell c of grid
+// row e (coarse face (q, f) next to finer leaves) is the face cell (a1, a2)
+// along the tangential axes; a cell on several level faces belongs to the row
+// of its lowest face index (returns false in the other rows), so each is
+// handled once, all its level faces together.
 __device__ __forceinline__ bool cf_cell(const DevProblem& P, const Geo& geo, int f, int c, int cc[3]) {
   const int d = f >> 1, side = f & 1;
   const int bd[3] = {P.bx, P.by, P.bz};
@@ -1689,6 +1615,76 @@ __device__ __forceinline__ bool cf_cell(const DevProblem& P, const Geo& geo, int
   cc[t1] = c - cc[t2] * bd[t1];
   cc[d] = side ? bd[d] - 1 : 0;
   return (level_faces(geo, P.nblocks, cc[0], cc[1], cc[2]) & ((1 << f) - 1)) == 0;
+}
+
+constexpr int kSmrCells = 51;  // face cells per k_smr_flux workgroup pass (5 threads each)
+
+// Flux correction (Sec. 2: the flux through a coarse face shared with finer
+// blocks is the finer blocks' flux): each level-0 cell on level faces adds,
+// for each of them in x, y, z order, c dt (F_coarse - mean F_fine) / dx on an
+// upper face, the opposite on a lower one, both fluxes recomputed from the
+// stage's source exactly as the stage kernel formed them. A cell belongs to
+// one grid row (cf_cell), so no cell is updated twice at once.
+template <int RECON, typename T>
+__global__ void __launch_bounds__(256) k_smr_flux(const DevProblem* __restrict__ Pp, int stage, int parity) {
+  const DevProblem& P = *Pp;
+  const int e = blockIdx.y;
+  const int q = P.cfinfo[2 * e], f = P.cfinfo[2 * e + 1];
+  const int d = f >> 1;
+  const RkStage& rs = P.rk[stage - 1];
+  const double* __restrict__ S = rs.src;
+  double* Out = rs.dst;
+  const double gamma = P.gamma, gm1 = gamma - 1.0;
+  const Gas<T> gas{T(gamma), T(gm1), T((gamma + 1.0) / (2.0 * gamma))};
+  const Floors fl{P.rho_floor, P.p_floor / gm1};
+  const double cst = rs.c * (P.cfl * __longlong_as_double((long long)P.dtmin[parity]));
+  const int bd[3] = {P.bx, P.by, P.bz};
+  Geo geo;
+  geo_init(geo, P, q);
+  // five threads per face cell: h = 0 the coarse flux, h = 1..4 the fine
+  // ones (more threads in flight than one thread doing all five)
+  __shared__ double sFl[kSmrCells][5][5];
+  const int cs = threadIdx.x / 5, h = threadIdx.x - 5 * cs;
+  const int area = (d == 0 ? P.by : P.bx) * (d == 2 ? P.by : P.bz);
+  for (int base = blockIdx.x * kSmrCells; base < area; base += gridDim.x * kSmrCells) {
+    const int c = base + cs;
+    int cc[3] = {0, 0, 0};
+    const bool mine = cs < kSmrCells && c < area && cf_cell(P, geo, f, c, cc);
+    const int lvf = mine ? level_faces(geo, P.nblocks, cc[0], cc[1], cc[2]) : 0;
+    for (int d2 = 0; d2 < 3; ++d2) {  // the same number of barriers in every thread
+      const int s2 = (lvf >> (2 * d2 + 1)) & 1;
+      const bool act = ((lvf >> (2 * d2)) & 3) != 0;  // a level face along d2 (one side at most)
+      const int u1 = d2 == 0 ? 1 : 0, u2 = d2 == 2 ? 1 : 2;
+      if (act) {
+        double fo[5];
+        if (h == 0) {
+          int lf[3] = {cc[0], cc[1], cc[2]};
+          lf[d2] = s2 ? bd[d2] : 0;  // face_pair's cell index: the face's upper cell
+          T fho[5], unused[5];
+          face_pair<RECON, T>(geo, fl, gas, S, d2, lf[0], lf[1], lf[2], fho, unused);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) fo[v] = (double)fho[v];
+        } else {
+          fine_face<RECON, T>(P, fl, gas, S, q, d2, s2, cc[u1], cc[u2], h - 1, false, fo);
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sFl[cs][h][v] = fo[v];
+      }
+      __syncthreads();
+      if (act && h == 0) {
+        const double idc = 1.0 / P.dx[d2];  // the coarse leaf is on level 0
+        const int64_t off = (int64_t)q * P.bstride + ((int64_t)cc[2] * P.by + cc[1]) * P.bx + cc[0];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const double fc = sFl[cs][0][v];
+          const double mean = ((sFl[cs][1][v] + sFl[cs][2][v]) + (sFl[cs][3][v] + sFl[cs][4][v])) * 0.25;
+          const double dl = s2 ? (fc - mean) * idc : (mean - fc) * idc;
+          Out[off + v * P.vstride] += cst * dl;
+        }
+      }
+      __syncthreads();  // sFl is reused by the next direction / group
+    }
+  }
 }
 
 // Before a stage that updates U in place: keep the step-start values of the
@@ -2077,7 +2073,7 @@ hipError_t launch_smr_cell(int recon, int prec, const DevProblem* p, int stage, 
 
 hipError_t launch_smr_flux(int recon, int prec, const DevProblem* p, int stage, int parity, int ncf,
                            const int32_t block[3], hipStream_t s) {
-  using K = void (*)(const DevProblem*, int, int, int);
+  using K = void (*)(const DevProblem*, int, int);
   static const K tab[4][2] = {{k_smr_flux<0, double>, k_smr_flux<0, float>},
                               {k_smr_flux<1, double>, k_smr_flux<1, float>},
                               {k_smr_flux<2, double>, k_smr_flux<2, float>},
@@ -2085,12 +2081,8 @@ hipError_t launch_smr_flux(int recon, int prec, const DevProblem* p, int stage, 
   if (recon < 0 || recon > 3 || prec < 0 || prec > 1) return hipErrorInvalidValue;
   const int area = std::max(block[1] * block[2], std::max(block[0] * block[2], block[0] * block[1]));
   const int gx = std::max(1, std::min((area + kSmrCells - 1) / kSmrCells, 1024));
-  for (int dir = 0; dir < 3; ++dir) {
-    hipLaunchKernelGGL(tab[recon][prec], dim3(gx, ncf), dim3(256), 0, s, p, stage, parity, dir);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  hipLaunchKernelGGL(tab[recon][prec], dim3(gx, ncf), dim3(256), 0, s, p, stage, parity);
+  return hipGetLastError();
 }
 
 
