@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--skip-fofc", action="store_true", help="skip the first-order flux correction lines")
     ap.add_argument("--fofc-only", action="store_true",
                     help="time only the first-order flux correction workloads (for profiling)")
+    ap.add_argument("--schemes-only", action="store_true",
+                    help="time only the higher-order schemes at 256^3 (for profiling)")
     ap.add_argument("--kh-only", action="store_true",
                     help="time only the 512^3 PPM4 workload (for profiling)")
     ap.add_argument("--headline-only", action="store_true",
@@ -169,6 +171,10 @@ def main():
 
     if args.kh_only:
         print(json.dumps({"kh512": run_kh512(run, P, hy, cpu=not args.skip_cpu)}), flush=True)
+        return
+
+    if args.schemes_only:
+        print(json.dumps({"schemes": run_schemes(run, pb, P, args.steps)}), flush=True)
         return
 
     if args.fofc_only:
