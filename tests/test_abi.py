@@ -116,6 +116,29 @@ def test_refined_leaves_and_workspace_without_gpu(box, periodic):
                                                     + tables + a(ncf * 64 * 5 * 8))
 
 
+@pytest.mark.parametrize("block,recon,per_block", [((12, 8, 16), 1, 2), ((16, 16, 16), 0, 8),
+                                                   ((6, 8, 10), 2, 2), ((12, 12, 12), 3, 4)])
+def test_ghost_slabs_packed_per_block_without_gpu(block, recon, per_block):
+    # a slab takes ghost depth x the largest block face cells per variable and
+    # the slabs are packed into whole blocks after the leaves, the largest
+    # power of two of them that fits: (12, 8, 16) with PPM4 holds 1536 cells
+    # per variable and a slab 3 x 192 = 576, so 2 per block; (16, 16, 16) with
+    # PLM 4096 / (2 x 256) = 8; (6, 8, 10) with WENO-Z 480 / (3 x 80) = 2;
+    # (12, 12, 12) with PPMX 1728 / (3 x 144) = 4
+    from paper_2409_16053_amd import hy
+    from paper_2409_16053_amd import problems as P
+    n = tuple(4 * b for b in block)
+    pb = P.uniform(n=n, rho=1.0, v=(0, 0, 0), p=1.0, bc=P.PERIODIC).with_(
+        block=block, recon=recon, refine=((1, 1, 1), (2, 2, 2)))
+    lv = hy.leaves(pb)
+    nvirt, ncf = _slab_faces(lv, (4, 4, 4), True)
+    a = lambda x: (x + 255) // 256 * 256
+    cells = block[0] * block[1] * block[2]
+    reg = a((len(lv) + (nvirt + per_block - 1) // per_block) * cells * 5 * 8)
+    tables = a(len(lv) * 12 * 4) + a(nvirt * 2 * 4 + 4) + a(64 * 2 * 4) + a(ncf * 2 * 4 + 4)
+    assert hy.workspace_bytes(pb) == 1024 + 2 * reg + tables
+
+
 @pytest.mark.parametrize("bad", [dict(block=(9, 8, 8), n=(36, 24, 16)),
                                  dict(refine=((0, 0, 0), (5, 1, 1))), dict(recon=3, block=(4, 8, 8)),
                                  dict(refine=(((0, 0, 0), (1, 1, 1)), ((1, 0, 0), (1, 1, 1)))),
