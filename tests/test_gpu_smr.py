@@ -288,3 +288,29 @@ def test_several_boxes_conserve_and_tile_shapes_bitwise(hy):
     tot = lambda U: np.einsum("q,qv->v", vol, U.reshape(U.shape[0], 5, -1).sum(-1))
     a = np.einsum("q,qv->v", vol, np.abs(pb.U).reshape(pb.U.shape[0], 5, -1).sum(-1))
     assert np.all(np.abs(tot(outs[0]) - tot(pb.U)) <= 1e-13 * a)
+
+
+# ------------------------------------------------------- packed ghost slabs
+@pytest.mark.parametrize("name", ["wenoz_min_blocks", "ppmx_corner_boxes"])
+def test_packed_slabs_edge_shapes(hy, name):
+    # ghost slabs packed 2 to a block: the smallest blocks refinement allows
+    # for a 3-deep ghost zone (6 x 8 x 10, WENO-Z), and 12^3 blocks with two
+    # refined corner boxes on an outflow mesh (PPMX); gate as for the random
+    # configurations (1e-12, or 100 x the one-ulp sensitivity)
+    from smr_cases import smooth
+    per = ((P.PERIODIC, P.PERIODIC),) * 3
+    out = ((P.OUTFLOW, P.OUTFLOW),) * 3
+    if name == "wenoz_min_blocks":
+        make = lambda s: smooth((24 * s, 32 * s, 40 * s), per, 21, (6, 8, 10), recon=P.WENOZ, rk=3)
+        pb = _refined(make, ((1, 1, 1), (3, 2, 3)))
+    else:
+        make = lambda s: smooth((36 * s, 36 * s, 36 * s), out, 22, (12, 12, 12), recon=P.PPMX, rk=2)
+        pb = _refined(make, (((0, 0, 0), (1, 1, 1)), ((2, 2, 2), (3, 3, 3))))
+    sens = one_ulp_sensitivity(oracle.advance, pb, 3)
+    gate = max(1e-12, 100 * sens)
+    U, q = _run(hy, pb, 3)
+    ref = oracle.advance(pb, 3)
+    r = _rel(U, ref["U"])
+    print(f"[{name}] rel L1 {r:.3e} (one-ulp sensitivity {sens:.2e}, gate {gate:.1e})", flush=True)
+    assert r <= gate and abs(q["dt"] / ref["dt"] - 1) <= max(1e-11, gate)
+    assert q["floor_hits"] == ref["floor_hits"]
